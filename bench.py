@@ -1,0 +1,160 @@
+#!/usr/bin/env python
+"""Throughput of the fractional PP-WCNS-IS step on one MI355X.
+
+A step is one SSP-RK3 step of the fractional algorithm: wavespeed and time
+step from W^n, three stages of the five-equation hyperbolic operator, each
+followed by the infinite-rate thermal relaxation.  Workload: the 2D shock on a
+liquid column with a gas bubble (three species, 1024 x 512 cells, FP64).
+
+Prints one JSON line.  Inputs are resident in HBM before the timed region.
+`roofline` describes the dominant kernel (the y-direction sweep, which also
+applies the stage update and the relaxation), timed live with HIP events on
+the stream it runs on.  `cpu_baseline` times the CPU oracle on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+METRIC = ("cell-updates/s per RK3 step (plain FP64 vs FP32 vs learned) at stated L1 error; HBM GB/s")
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector, dense
+PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
+
+
+def node_flops(N, D):
+    """Primitive state of one node (hot-path step a1)."""
+    return 8 * N + 3 * D + 7
+
+
+def face_flops(N, D):
+    """Algorithmic FP64 operations of one midpoint (add, sub, mul, div, sqrt,
+    tanh count one each; comparisons, min/max and |x| count zero; limiter
+    branches that fire only on bad faces count zero).  Breakdown in the design doc."""
+    M = 2 * N + D
+    return 253 * M + 141 * N + 56 * D + 251
+
+
+def cell_flops(N, D, final):
+    """Flux difference per direction; stage update and relaxation in the last one."""
+    M = 2 * N + D
+    f = 2 * M + (M if D > 1 else 0)
+    if final:
+        f += 4 * M + (12 * N + 2 * D + 25)
+    return f
+
+
+def sweep_flops(N, D, n, direction, final):
+    """Algorithmic FP64 operations of one launch of the sweep in `direction`."""
+    cells = 1
+    for k in n:
+        cells *= k
+    faces = cells // n[direction] * (n[direction] + 1)
+    return faces * face_flops(N, D) + cells * (node_flops(N, D) + cell_flops(N, D, final))
+
+
+def algorithmic_bytes_per_cell_step(M):
+    """Stage 1 reads W^n, writes W1; stages 2, 3 read W^(s) and W^n, write the
+    next state: 8 M doubles per cell per RK3 step."""
+    return 64 * M
+
+
+def cpu_baseline(prob, budget_s=12.0, max_steps=20):
+    import oracle
+    oracle.build(force=False)
+    threads = oracle.Oracle.set_threads(0)
+    o = oracle.from_problem(prob)
+    W = prob.W
+    t0 = time.perf_counter()
+    steps = 0
+    while steps < max_steps:
+        W, _ = o.step(W, cfl=prob.cfl)
+        steps += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    return {"value": prob.ncell * steps / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} SSP-RK3 steps of the full {prob.n[0]}x{prob.n[1]} workload from its initial "
+                      f"condition, OpenMP over grid lines, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--nx", type=int, default=1024)
+    ap.add_argument("--ny", type=int, default=512)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (DESIGN.md describes how it "
+              "would shard). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2208_04488_amd import hrm
+    from paper_2208_04488_amd import inputs as I
+
+    prob = I.config2(args.nx, args.ny)
+    N, D, M = prob.N, prob.D, prob.M
+    s = hrm.Solver(prob, flags=hrm.FUSE_RELAX)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        s.step(cfl=prob.cfl)
+    torch.cuda.synchronize()
+
+    # timed region; the sweeps are bracketed by HIP events on the same stream
+    hrm.hrm_set_timing(s.ctx, (1 << 0) | (1 << 1))
+    hrm.hrm_get_timing(s.ctx)  # clear
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        s.step(cfl=prob.cfl)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_total = ev0.elapsed_time(ev1)
+    timers = hrm.hrm_get_timing(s.ctx)
+    hrm.hrm_set_timing(s.ctx, 0)
+    diag = s.diagnostics()
+    ms_step = ms_total / args.steps
+
+    # dominant kernel: the sweep with the larger total time
+    kname = max(("sweep_x", "sweep_y"), key=lambda k: timers[k][0])
+    kdir = 0 if kname == "sweep_x" else 1
+    ms_launch = timers[kname][0] / max(timers[kname][1], 1)
+    flops = sweep_flops(N, D, prob.n, kdir, final=(kdir == D - 1))
+    achieved = flops / (ms_launch * 1e-3) / 1e12
+    cups = prob.ncell * args.steps / (ms_total * 1e-3)
+    hbm = algorithmic_bytes_per_cell_step(M) * cups / 1e9
+
+    out = {
+        "metric": METRIC, "value": cups, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"2D Mach-1.47 shock on a liquid column with a gas bubble, 3 species, "
+                               f"{prob.n[0]}x{prob.n[1]} cells, FP64 PP-WCNS-IS + thermal relaxation, CFL 0.4",
+                   "cells": prob.ncell, "species": N, "dim": D, "components": M},
+        "roofline": {"bound": "alu", "kernel": f"k_sweep direction {kdir} (N={N}, D={D})",
+                     "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "flops_per_launch": flops, "ms_per_launch": ms_launch},
+        "hbm_gbs_algorithmic": hbm, "hbm_frac_algorithmic": hbm / PEAK_HBM_GBS,
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in timers.items() if v[1]},
+        "wall_s_timed": wall,
+        "positivity": {"relax_bad": diag["relax_bad"], "interp_hs": diag["interp_hs"],
+                       "flux_hs": diag["flux_hs"]},
+    }
+    s.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

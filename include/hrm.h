@@ -1,0 +1,192 @@
+/*
+ * hrm.h -- C-ABI of the MI355X (gfx950) library for the hot path of the
+ * positivity-preserving fractional algorithm for the four-equation HRM
+ * (Wong, Angel & Kiris, arXiv:2208.04488): one hyperbolic SSP-RK stage of the
+ * five-equation model with PP-WCNS-IS, followed by the algebraic
+ * infinite-rate thermal relaxation.
+ *
+ * Conventions common to every call
+ *  - State arrays are caller-owned DEVICE pointers to double, laid out
+ *    structure-of-arrays as W[c][z][y][x] (x fastest), interior cells only,
+ *    ncell = n[0]*n[1]*n[2].  Component order is the conservative vector of
+ *    Sec. 2: alpha_k rho_k (k = 0..N-1), rho u_d (d = 0..dim-1), E,
+ *    alpha_k (k = 0..N-2); M = 2N + dim components.  Ghost cells do not
+ *    exist in memory: boundary conditions are applied when tiles are loaded.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Every call only enqueues work on that stream and returns; device errors
+ *    of a kernel surface at the next synchronising call.
+ *  - Calls return an int status: HRM_OK, or an error code with a message
+ *    readable through hrm_last_error().  No exception crosses the ABI.
+ *  - Calls on one context are not thread-safe; use one context per thread.
+ */
+#ifndef HRM_H
+#define HRM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HRM_MAX_SPECIES 8
+
+/* status codes */
+#define HRM_OK 0
+#define HRM_EINVAL 1        /* bad sizes, EOS, stage index, aliasing, NULL pointer */
+#define HRM_ENOMEM 2        /* device allocation failed */
+#define HRM_EDEVICE 3       /* a HIP runtime call failed (message in hrm_last_error) */
+#define HRM_EADMISSIBLE 4   /* hrm_get_diagnostics: relaxation met states outside script-G */
+#define HRM_EUNSUPPORTED 5  /* (N, dim, precision, weights) combination not built */
+
+/* boundary conditions per side (Sec. 5: extrapolation / periodic) */
+#define HRM_BC_TRANSMISSIVE 0
+#define HRM_BC_PERIODIC 1
+
+/* face arithmetic precision; the state, relaxation, limiter bound checks and
+ * the accumulation are double in both */
+#define HRM_FP64 0
+#define HRM_FP32 1
+
+/* nonlinear weights of the interpolation */
+#define HRM_WEIGHTS_IS 0  /* incremental-stencil WENO weights (App. C) */
+
+/* grid flags */
+#define HRM_NO_LIMITERS 1   /* skip the interpolation and flux limiters (Sec. 4.3.2) */
+#define HRM_NO_BLEND 2      /* shock-sensor blending off: pure HCS flux (App. B) */
+#define HRM_FIRST_ORDER 4   /* first-order HLLC fluxes only (Sec. 4.1.1) */
+#define HRM_FUSE_RELAX 8    /* hrm_rk_stage relaxes its output in the same kernel */
+
+/* Uniform Cartesian grid of n[0] x n[1] x n[2] cells, nodes at cell centres
+ * (Sec. 4.1).  Entries beyond `dim` must be n = 1. */
+typedef struct {
+    int dim;               /* D = 1, 2 or 3 */
+    int n[3];              /* cells per direction */
+    double dx[3];          /* spacing per direction (> 0) */
+    int bc_lo[3], bc_hi[3];
+    int precision;         /* HRM_FP64 or HRM_FP32 */
+    int weights;           /* HRM_WEIGHTS_IS */
+    int flags;             /* HRM_NO_LIMITERS | HRM_NO_BLEND | HRM_FIRST_ORDER | HRM_FUSE_RELAX */
+} hrm_grid;
+
+/* Stiffened-gas species (eq:species_stiffened_EOS): gamma_k > 1, c_v,k > 0,
+ * p_inf,k >= 0, q_k.  Species 0 is the liquid; species 1..N-1 must have
+ * p_inf = 0 (the relaxation of Sec. 4.2 assumes one stiffened gas). */
+typedef struct {
+    int nspecies;          /* N >= 2 */
+    double gamma[HRM_MAX_SPECIES];
+    double cv[HRM_MAX_SPECIES];
+    double pinf[HRM_MAX_SPECIES];
+    double q[HRM_MAX_SPECIES];
+} hrm_eos;
+
+/* Tolerances and constants; hrm_default_params() fills the paper's values:
+ * WENO eps 1e-15 (App. C); interpolation limiter eps 1e-10, 1e-10 and hard
+ * switch 1e-11, 1e-11, 1e-9 (Sec. 4.3.2); flux limiter eps 1e-10, 1e-10,
+ * 1e-8 and hard switch 1e-11, 1e-11, 1e-9 (Sec. 4.3.2); sensor C_s = 1e12,
+ * q = 2 and HCS psi = 256/175 (Sec. 4.3.1). */
+typedef struct {
+    double eps_weno;
+    double eps_i_ar, eps_i_a;
+    double hs_i_ar, hs_i_a, hs_i_rc2;
+    double eps_f_ar, eps_f_a, eps_f_re;
+    double hs_f_ar, hs_f_a, hs_f_re;
+    double Cs, qexp, psi;
+} hrm_params;
+
+/* Device-side counters, read by hrm_get_diagnostics (which synchronises). */
+typedef struct {
+    unsigned long long alg1;       /* interpolated partial densities blended (Alg. 1) */
+    unsigned long long alg2;       /* interpolated volume fractions blended (Alg. 2) */
+    unsigned long long interp_hs;  /* interpolation hard switch fired */
+    unsigned long long alg3;       /* faces with theta < 1 in Alg. 3 */
+    unsigned long long alg4;       /* faces with theta < 1 in Alg. 4 */
+    unsigned long long flux_hs;    /* flux hard switch fired */
+    unsigned long long relax_bad;  /* relaxation inputs outside script-G (left unchanged) */
+    unsigned long long reserved;
+} hrm_diag;
+
+typedef struct hrm_ctx hrm_ctx;
+
+/* Fill `p` with the paper's tolerances and constants. */
+void hrm_default_params(hrm_params* p);
+
+/* Validate grid and EOS, copy them into the context and allocate the
+ * library's scratch on the current device: one M x ncell right-hand-side
+ * buffer (dim > 1), two M x ncell stage buffers for hrm_step, wavespeed
+ * partials and the counters.  `params` NULL means hrm_default_params().
+ * On failure *out is NULL and the code says why (no message store exists). */
+int hrm_create(const hrm_grid* grid, const hrm_eos* eos, const hrm_params* params, hrm_ctx** out);
+
+/* Free the context and its scratch (synchronises the device first). */
+int hrm_destroy(hrm_ctx* ctx);
+
+/* Message of the last failed call on this context ("" if none). */
+const char* hrm_last_error(const hrm_ctx* ctx);
+
+/* Sec. 4.1.2: d_out[d] = max over cells of |u_d| + c (five-equation mixture
+ * sound speed), d = 0..dim-1.  d_W: M x ncell doubles; d_out: dim doubles. */
+int hrm_max_wavespeed(hrm_ctx* ctx, const double* d_W, double* d_out, void* stream);
+
+/* Sec. 4.1.2 multi-dimensional step: tau_d = d_maxspeed[d]/dx_d,
+ * dt = CFL / sum tau (or dt_fixed if > 0), sigma_d = tau_d / sum tau,
+ * lambda_d = dt / (sigma_d dx_d).  If t_end > 0 the step is clipped so that
+ * the device time d_slot[4] does not pass t_end, and d_slot[4] advances by dt.
+ * Writes d_slot = (dt, lambda_0, lambda_1, lambda_2, t) on the device. */
+int hrm_compute_dt(hrm_ctx* ctx, const double* d_maxspeed, double cfl, double dt_fixed, double t_end,
+                   double* d_slot, void* stream);
+
+/* Semi-discrete right-hand side (eq:semi_W_G_pm_eqn) of state d_W:
+ *   d_L_i = - sum_d (G^{**,-}_{i+1/2} - G^{**,+}_{i-1/2}) / dx_d
+ * with the limiters' lambda_d read from d_slot[1 + d].  d_L: M x ncell. */
+int hrm_rhs(hrm_ctx* ctx, const double* d_W, double* d_L, const double* d_slot, void* stream);
+
+/* One SSP-RK3 stage in Shu-Osher form (stage = 0, 1, 2; Sec. 4.4):
+ *   d_Wout = a_s d_Wn + b_s (d_Ws + dt L(d_Ws)),
+ *   (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3), dt = d_slot[0],
+ * followed by the thermal relaxation when the grid has HRM_FUSE_RELAX.
+ * d_Wout may alias d_Wn (read point-wise) but must not alias d_Ws. */
+int hrm_rk_stage(hrm_ctx* ctx, int stage, const double* d_Wn, const double* d_Ws, double* d_Wout,
+                 const double* d_slot, void* stream);
+
+/* Sec. 4.2: in-place infinite-rate thermal relaxation of every cell; only the
+ * volume-fraction components change.  Cells with rho(e - qbar) <= 0 are left
+ * unchanged and counted in hrm_diag.relax_bad. */
+int hrm_relax(hrm_ctx* ctx, double* d_W, void* stream);
+
+/* One full SSP-RK3 step of the fractional algorithm on d_W in place:
+ * wavespeed of W^n, time step into d_slot (see hrm_compute_dt), three stages
+ * each followed by the relaxation.  Uses the context's stage buffers. */
+int hrm_step(hrm_ctx* ctx, double* d_W, double cfl, double dt_fixed, double t_end, double* d_slot,
+             void* stream);
+
+/* Copy the counters to *out (synchronises the stream of the last call).
+ * Returns HRM_EADMISSIBLE if relax_bad > 0, else HRM_OK. */
+int hrm_get_diagnostics(hrm_ctx* ctx, hrm_diag* out);
+
+/* Zero the counters (enqueued on `stream`, by a kernel). */
+int hrm_reset_diagnostics(hrm_ctx* ctx, void* stream);
+
+/* Opt-in kernel timing with HIP events recorded on the caller's stream
+ * around each launch of the selected kinds (bit k of `mask` selects kind k).
+ * For measurement only: event records add a few microseconds per launch.
+ * When more than 4096 launches are pending the recording call synchronises
+ * its stream to fold them into the totals. */
+#define HRM_T_SWEEP_X 0    /* k_sweep, direction 0 */
+#define HRM_T_SWEEP_Y 1    /* k_sweep, direction 1 */
+#define HRM_T_SWEEP_Z 2    /* k_sweep, direction 2 */
+#define HRM_T_WAVESPEED 3  /* wavespeed partial maxima + final reduction */
+#define HRM_T_DT 4         /* time-step kernel */
+#define HRM_T_RELAX 5      /* stand-alone relaxation */
+#define HRM_NTIMERS 6
+int hrm_set_timing(hrm_ctx* ctx, int mask);
+
+/* Synchronise, then write the summed milliseconds and launch counts per kind
+ * since the last call into ms[HRM_NTIMERS] and counts[HRM_NTIMERS]; the
+ * totals restart from zero. */
+int hrm_get_timing(hrm_ctx* ctx, double* ms, long long* counts);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HRM_H */

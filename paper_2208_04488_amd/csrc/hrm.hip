@@ -1,0 +1,751 @@
+// hrm.hip -- gfx950 kernels and the C-ABI of the PP-WCNS-IS stage and the
+// thermal relaxation (arXiv:2208.04488).  Declarations and semantics of the
+// exported calls are in include/hrm.h.
+//
+// Kernels
+//   k_sweep<N,D,DIR>  one direction of the spatial operator.  A block stages
+//                     the primitive data of a tile of nodes (with the 3-node
+//                     halo on both sides, boundary conditions applied at load)
+//                     in LDS, computes one face per thread, writes the face
+//                     pairs back to LDS and forms the flux difference of each
+//                     cell.  The last direction also applies the Shu-Osher
+//                     stage update and, optionally, the relaxation.
+//   k_relax           point-wise relaxation.
+//   k_wavespeed       per-block max of |u_d| + c, then k_reduce_max.
+//   k_dt              the time step and lambda_d on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "hrm.h"
+#include "hrm_face.hpp"
+
+namespace hrm {
+
+struct SweepArgs {
+    const double* Ws;
+    const double* Wn;
+    double* Wout;
+    double* rhs;
+    const double* slot;
+    unsigned long long* cnt;
+    long long ncell;
+    int n[3];
+    int bclo, bchi;
+    int mode;  // 0: rhs = L_d, 1: rhs += L_d, 2: stage update with rhs + L_d
+    int relax;
+    double a, b;
+    double idx;
+    EosDev e;
+    ParDev P;
+};
+
+constexpr int MODE_WRITE = 0, MODE_ADD = 1, MODE_FINAL = 2;
+
+__device__ inline int map_bc(int g, int n, int lo, int hi)
+{
+    if (g < 0) return lo == HRM_BC_PERIODIC ? ((g % n) + n) % n : 0;
+    if (g >= n) return hi == HRM_BC_PERIODIC ? g % n : n - 1;
+    return g;
+}
+
+// sum each counter over the wave, one atomic per non-zero counter
+__device__ inline void flush_counters(const unsigned* c, unsigned long long* dst)
+{
+#pragma unroll
+    for (int k = 0; k < C_N; ++k) {
+        unsigned long long v = c[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (__lane_id() == 0 && v != 0ull) atomicAdd(&dst[k], v);
+    }
+}
+
+// Tile: BS face threads along the sweep direction (BS-1 cells), BA threads
+// across it.  DIR == 0: blockDim = (BS, BA), across = y, blockIdx.z = z.
+// DIR == 1: blockDim = (BA, BS), across = x, blockIdx.z = z.
+// DIR == 2: blockDim = (BA, BS), across = x, blockIdx.y = y.
+template <int N, int D, int DIR, int BS, int BA>
+__global__ void __launch_bounds__(BS* BA) k_sweep(const SweepArgs A)
+{
+    using F = NodeFields<N, D>;
+    constexpr int M = 2 * N + D, IA = N + D + 1;
+    constexpr int NA = N > 1 ? N - 1 : 1;
+    constexpr int LN = BS + 5;
+    constexpr int FS = BA * LN;
+    constexpr int NS = DIR == 0 ? 1 : BA;
+    __shared__ double lds[F::COUNT * FS];
+
+    const int ts = DIR == 0 ? threadIdx.x : threadIdx.y;
+    const int ta = DIR == 0 ? threadIdx.y : threadIdx.x;
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    const long long st[3] = {1, A.n[0], (long long)A.n[0] * A.n[1]};
+    int c0, abase, other, adim, odim;
+    if (DIR == 0) {
+        c0 = blockIdx.x * (BS - 1);
+        abase = blockIdx.y * BA;
+        other = blockIdx.z;
+        adim = 1;
+        odim = 2;
+    } else if (DIR == 1) {
+        c0 = blockIdx.y * (BS - 1);
+        abase = blockIdx.x * BA;
+        other = blockIdx.z;
+        adim = 0;
+        odim = 2;
+    } else {
+        c0 = blockIdx.z * (BS - 1);
+        abase = blockIdx.x * BA;
+        other = blockIdx.y;
+        adim = 0;
+        odim = 1;
+    }
+    const int nsw = A.n[DIR], na = A.n[adim];
+    const long long nc = A.ncell;
+    auto base = [](int a, int l) { return DIR == 0 ? a * LN + l : l * BA + a; };
+
+    // stage the node tile (sweep index c0-3 .. c0+BS+1) with its primitives
+    for (int q = tid; q < LN * BA; q += BS * BA) {
+        const int l = DIR == 0 ? q % LN : q / BA;
+        const int a = DIR == 0 ? q / LN : q % BA;
+        const int g = map_bc(c0 - 3 + l, nsw, A.bclo, A.bchi);
+        const int ca = min(abase + a, na - 1);
+        const long long cell = g * st[DIR] + ca * st[adim] + other * st[odim];
+        double W[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) W[c] = A.Ws[c * nc + cell];
+        St<N, D> s;
+        state_from_W<N, D>(A.e, W, s);
+        const int b = base(a, l);
+#pragma unroll
+        for (int c = 0; c < M; ++c) lds[c * FS + b] = W[c];
+#pragma unroll
+        for (int d = 0; d < D; ++d) lds[(F::U + d) * FS + b] = s.u[d];
+        lds[F::P * FS + b] = s.p;
+        lds[F::RHO * FS + b] = s.rho;
+        lds[F::C * FS + b] = s.c;
+        lds[F::RC2 * FS + b] = s.rc2;
+    }
+    __syncthreads();
+
+    // one face per thread: between sweep nodes c0-1+ts and c0+ts
+    unsigned cnt[C_N] = {0, 0, 0, 0, 0, 0, 0};
+    double G[M], Gp[NA];
+    {
+        unsigned lc[C_N] = {0, 0, 0, 0, 0, 0, 0};
+        face_flux<N, D, DIR, NS, FS>(lds + base(ta, ts), A.e, A.P, A.slot[1 + DIR], G, Gp, lc);
+        const bool ok = (c0 - 1 + ts <= nsw - 1) && (abase + ta < na);
+        if (ok)
+#pragma unroll
+            for (int k = 0; k < C_N; ++k) cnt[k] += lc[k];
+    }
+    __syncthreads();
+    {
+        const int b = base(ta, ts);
+#pragma unroll
+        for (int c = 0; c < M; ++c) lds[c * FS + b] = G[c];
+#pragma unroll
+        for (int k = 0; k < N - 1; ++k) lds[(M + k) * FS + b] = Gp[k];
+    }
+    __syncthreads();
+
+    // flux difference of cell c0+ts: faces ts (i-1/2) and ts+1 (i+1/2)
+    const int ci = c0 + ts, ca = abase + ta;
+    if (ts < BS - 1 && ci < nsw && ca < na) {
+        const long long cell = ci * st[DIR] + ca * st[adim] + other * st[odim];
+        const int bl = base(ta, ts), br = base(ta, ts + 1);
+        double L[M];
+#pragma unroll
+        for (int c = 0; c < IA; ++c) L[c] = -(lds[c * FS + br] - lds[c * FS + bl]) * A.idx;
+#pragma unroll
+        for (int k = 0; k < N - 1; ++k) L[IA + k] = -(lds[(IA + k) * FS + br] - lds[(M + k) * FS + bl]) * A.idx;
+        if (A.mode == MODE_WRITE) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) A.rhs[c * nc + cell] = L[c];
+        } else if (A.mode == MODE_ADD) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) A.rhs[c * nc + cell] += L[c];
+        } else {
+            const double dt = A.slot[0];
+            double w[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                const double Lc = D > 1 ? A.rhs[c * nc + cell] + L[c] : L[c];
+                w[c] = A.a * A.Wn[c * nc + cell] + A.b * (A.Ws[c * nc + cell] + dt * Lc);
+            }
+            if (A.relax && !relax_cell<N, D>(A.e, w)) cnt[C_RELAX_BAD]++;
+#pragma unroll
+            for (int c = 0; c < M; ++c) A.Wout[c * nc + cell] = w[c];
+        }
+    }
+    flush_counters(cnt, A.cnt);
+}
+
+template <int N, int D>
+__global__ void __launch_bounds__(256) k_relax(double* W, long long nc, EosDev e, unsigned long long* cnt)
+{
+    constexpr int M = 2 * N + D;
+    unsigned c[C_N] = {0, 0, 0, 0, 0, 0, 0};
+    for (long long i = blockIdx.x * 256ll + threadIdx.x; i < nc; i += (long long)gridDim.x * 256) {
+        double w[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) w[k] = W[k * nc + i];
+        if (relax_cell<N, D>(e, w)) {
+#pragma unroll
+            for (int k = 0; k < N - 1; ++k) W[(N + D + 1 + k) * nc + i] = w[N + D + 1 + k];
+        } else {
+            c[C_RELAX_BAD]++;
+        }
+    }
+    flush_counters(c, cnt);
+}
+
+// NaN-propagating max (a NaN anywhere makes the result NaN)
+__device__ inline double nmax(double a, double b) { return a != a ? a : (b != b ? b : fmax(a, b)); }
+
+template <int D>
+__device__ inline void block_max(double* m, double* sh)
+{
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) m[d] = nmax(m[d], __shfl_xor(m[d], off, 64));
+    const int w = threadIdx.x >> 6;
+    if (__lane_id() == 0)
+#pragma unroll
+        for (int d = 0; d < D; ++d) sh[w * D + d] = m[d];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i)
+#pragma unroll
+            for (int d = 0; d < D; ++d) m[d] = nmax(m[d], sh[i * D + d]);
+}
+
+template <int N, int D>
+__global__ void __launch_bounds__(256) k_wavespeed(const double* W, long long nc, EosDev e, double* part)
+{
+    constexpr int M = 2 * N + D;
+    __shared__ double sh[4 * 3];
+    double m[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) m[d] = 0.0;
+    for (long long i = blockIdx.x * 256ll + threadIdx.x; i < nc; i += (long long)gridDim.x * 256) {
+        double w[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) w[k] = W[k * nc + i];
+        St<N, D> s;
+        state_from_W<N, D>(e, w, s);
+#pragma unroll
+        for (int d = 0; d < D; ++d) m[d] = nmax(m[d], fabs(s.u[d]) + s.c);
+    }
+    block_max<D>(m, sh);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int d = 0; d < D; ++d) part[blockIdx.x * D + d] = m[d];
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_reduce_max(const double* part, int nb, double* out)
+{
+    __shared__ double sh[4 * 3];
+    double m[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) m[d] = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256)
+#pragma unroll
+        for (int d = 0; d < D; ++d) m[d] = nmax(m[d], part[i * D + d]);
+    block_max<D>(m, sh);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int d = 0; d < D; ++d) out[d] = m[d];
+}
+
+__global__ void k_dt(const double* maxs, int D, double dx0, double dx1, double dx2, double cfl, double dt_fixed,
+                     double t_end, double* slot)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double dx[3] = {dx0, dx1, dx2};
+    double tau[3] = {0.0, 0.0, 0.0}, ts = 0.0;
+    for (int d = 0; d < D; ++d) {
+        tau[d] = maxs[d] / dx[d];
+        ts += tau[d];
+    }
+    double dt = dt_fixed > 0.0 ? dt_fixed : cfl / ts;
+    const double t = slot[4];
+    if (t_end > 0.0 && t + dt > t_end) dt = fmax(t_end - t, 0.0);
+    slot[0] = dt;
+    for (int d = 0; d < 3; ++d) slot[1 + d] = d < D ? dt / ((tau[d] / ts) * dx[d]) : 0.0;
+    slot[4] = t_end > 0.0 && t + dt >= t_end ? t_end : t + dt;
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
+
+}  // namespace hrm
+
+// ------------------------------------------------------------------ context
+struct hrm_ctx {
+    int N, D, M;
+    int n[3];
+    double dx[3];
+    int bclo[3], bchi[3];
+    int precision, weights, flags;
+    long long ncell;
+    hrm::EosDev eos;
+    hrm::ParDev par;
+    double* d_rhs;
+    double* d_W1;
+    double* d_W2;
+    double* d_part;
+    int npart;
+    double* d_maxs;
+    unsigned long long* d_cnt;
+    hipStream_t last_stream;
+    // opt-in event timing
+    int timing_mask;
+    int npending;
+    int pend_kind[4096];
+    hipEvent_t pend_ev[4096][2];
+    hipEvent_t pool[4096][2];
+    int pool_ready;
+    double tms[HRM_NTIMERS];
+    long long tcnt[HRM_NTIMERS];
+    char err[512];
+};
+
+namespace {
+
+int fail(hrm_ctx* c, int code, const char* fmt, const char* a = "", long long v = 0)
+{
+    if (c) snprintf(c->err, sizeof(c->err), fmt, a, v);
+    return code;
+}
+
+int check_launch(hrm_ctx* c, const char* what)
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        snprintf(c->err, sizeof(c->err), "%s: %s", what, hipGetErrorString(e));
+        return HRM_EDEVICE;
+    }
+    return HRM_OK;
+}
+
+void fold_timers(hrm_ctx* c)
+{
+    for (int i = 0; i < c->npending; ++i) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, c->pend_ev[i][0], c->pend_ev[i][1]) == hipSuccess) {
+            c->tms[c->pend_kind[i]] += ms;
+            c->tcnt[c->pend_kind[i]] += 1;
+        }
+    }
+    c->npending = 0;
+}
+
+// records an event pair around the launches in its scope when `kind` is selected
+struct TimerScope {
+    hrm_ctx* c;
+    int kind;
+    hipStream_t s;
+    int slot;
+    TimerScope(hrm_ctx* c_, int kind_, hipStream_t s_) : c(c_), kind(kind_), s(s_), slot(-1)
+    {
+        if (!c->pool_ready || !((c->timing_mask >> kind) & 1)) return;
+        if (c->npending == 4096) {
+            (void)hipStreamSynchronize(s);
+            fold_timers(c);
+        }
+        slot = c->npending++;
+        c->pend_kind[slot] = kind;
+        c->pend_ev[slot][0] = c->pool[slot][0];
+        c->pend_ev[slot][1] = c->pool[slot][1];
+        (void)hipEventRecord(c->pend_ev[slot][0], s);
+    }
+    ~TimerScope()
+    {
+        if (slot >= 0) (void)hipEventRecord(c->pend_ev[slot][1], s);
+    }
+};
+
+template <int N, int D>
+struct Ops {
+    static constexpr int M = 2 * N + D;
+
+    template <int DIR, int BS, int BA>
+    static void launch_dir(hrm_ctx* c, hrm::SweepArgs& A, hipStream_t s)
+    {
+        dim3 blk = DIR == 0 ? dim3(BS, BA) : dim3(BA, BS);
+        const int cells = BS - 1;
+        dim3 grd;
+        if (DIR == 0)
+            grd = dim3((c->n[0] + cells - 1) / cells, (c->n[1] + BA - 1) / BA, c->n[2]);
+        else if (DIR == 1)
+            grd = dim3((c->n[0] + BA - 1) / BA, (c->n[1] + cells - 1) / cells, c->n[2]);
+        else
+            grd = dim3((c->n[0] + BA - 1) / BA, c->n[1], (c->n[2] + cells - 1) / cells);
+        A.bclo = c->bclo[DIR];
+        A.bchi = c->bchi[DIR];
+        A.idx = 1.0 / c->dx[DIR];
+        TimerScope t(c, HRM_T_SWEEP_X + DIR, s);
+        hipLaunchKernelGGL((hrm::k_sweep<N, D, DIR, BS, BA>), grd, blk, 0, s, A);
+    }
+
+    static void sweep(hrm_ctx* c, int dir, hrm::SweepArgs& A, hipStream_t s)
+    {
+        if constexpr (D == 1) {
+            launch_dir<0, 256, 1>(c, A, s);
+        } else {
+            if (dir == 0) launch_dir<0, 64, 4>(c, A, s);
+            if (dir == 1) launch_dir<1, 16, 16>(c, A, s);
+            if constexpr (D >= 3)
+                if (dir == 2) launch_dir<2, 16, 16>(c, A, s);
+        }
+    }
+
+    static void relax(hrm_ctx* c, double* W, hipStream_t s)
+    {
+        const long long nb = std::min<long long>((c->ncell + 255) / 256, 8192);
+        TimerScope t(c, HRM_T_RELAX, s);
+        hipLaunchKernelGGL((hrm::k_relax<N, D>), dim3((unsigned)nb), dim3(256), 0, s, W, c->ncell, c->eos, c->d_cnt);
+    }
+
+    static void wavespeed(hrm_ctx* c, const double* W, double* out, hipStream_t s)
+    {
+        TimerScope t(c, HRM_T_WAVESPEED, s);
+        hipLaunchKernelGGL((hrm::k_wavespeed<N, D>), dim3(c->npart), dim3(256), 0, s, W, c->ncell, c->eos, c->d_part);
+        hipLaunchKernelGGL((hrm::k_reduce_max<D>), dim3(1), dim3(256), 0, s, c->d_part, c->npart, out);
+    }
+};
+
+template <typename Fn>
+int dispatch(hrm_ctx* c, Fn&& fn)
+{
+    switch (c->N * 10 + c->D) {
+    case 21: fn(Ops<2, 1>()); return HRM_OK;
+    case 22: fn(Ops<2, 2>()); return HRM_OK;
+    case 23: fn(Ops<2, 3>()); return HRM_OK;
+    case 31: fn(Ops<3, 1>()); return HRM_OK;
+    case 32: fn(Ops<3, 2>()); return HRM_OK;
+    case 33: fn(Ops<3, 3>()); return HRM_OK;
+    default: return fail(c, HRM_EUNSUPPORTED, "N=%s%lld with this dim is not built", "", c->N);
+    }
+}
+
+hrm::SweepArgs base_args(hrm_ctx* c)
+{
+    hrm::SweepArgs A;
+    memset(&A, 0, sizeof(A));
+    A.cnt = c->d_cnt;
+    A.ncell = c->ncell;
+    for (int d = 0; d < 3; ++d) A.n[d] = c->n[d];
+    A.e = c->eos;
+    A.P = c->par;
+    return A;
+}
+
+// all directions of L(W_s); the last one runs in `final_mode`
+int run_operator(hrm_ctx* c, const double* Ws, const double* Wn, double* Wout, double* rhs, const double* slot,
+                 bool stage, double a, double b, int relax, hipStream_t s)
+{
+    hrm::SweepArgs A = base_args(c);
+    A.Ws = Ws;
+    A.Wn = Wn;
+    A.Wout = Wout;
+    A.rhs = rhs;
+    A.slot = slot;
+    A.a = a;
+    A.b = b;
+    A.relax = relax;
+    int rc = HRM_OK;
+    for (int d = 0; d < c->D; ++d) {
+        const bool last = d == c->D - 1;
+        A.mode = (stage && last) ? hrm::MODE_FINAL : (d == 0 ? hrm::MODE_WRITE : hrm::MODE_ADD);
+        rc = dispatch(c, [&](auto ops) { decltype(ops)::sweep(c, d, A, s); });
+        if (rc != HRM_OK) return rc;
+        if ((rc = check_launch(c, "sweep")) != HRM_OK) return rc;
+    }
+    return rc;
+}
+
+bool valid_ptr(const void* p) { return p != nullptr; }
+
+}  // namespace
+
+extern "C" {
+
+void hrm_default_params(hrm_params* p)
+{
+    if (!p) return;
+    p->eps_weno = 1e-15;
+    p->eps_i_ar = 1e-10;
+    p->eps_i_a = 1e-10;
+    p->hs_i_ar = 1e-11;
+    p->hs_i_a = 1e-11;
+    p->hs_i_rc2 = 1e-9;
+    p->eps_f_ar = 1e-10;
+    p->eps_f_a = 1e-10;
+    p->eps_f_re = 1e-8;
+    p->hs_f_ar = 1e-11;
+    p->hs_f_a = 1e-11;
+    p->hs_f_re = 1e-9;
+    p->Cs = 1e12;
+    p->qexp = 2.0;
+    p->psi = 256.0 / 175.0;
+}
+
+const char* hrm_last_error(const hrm_ctx* ctx) { return ctx ? ctx->err : "NULL context"; }
+
+int hrm_create(const hrm_grid* g, const hrm_eos* e, const hrm_params* prm, hrm_ctx** out)
+{
+    if (!out) return HRM_EINVAL;
+    *out = nullptr;
+    if (!g || !e) return HRM_EINVAL;
+    if (g->dim < 1 || g->dim > 3) return HRM_EINVAL;
+    if (e->nspecies < 2 || e->nspecies > HRM_MAX_SPECIES) return HRM_EINVAL;
+    for (int d = 0; d < 3; ++d) {
+        if (g->n[d] < 1 || (d >= g->dim && g->n[d] != 1)) return HRM_EINVAL;
+        if (d < g->dim && !(g->dx[d] > 0.0)) return HRM_EINVAL;
+        if (d < g->dim) {
+            for (int side = 0; side < 2; ++side) {
+                const int bc = side ? g->bc_hi[d] : g->bc_lo[d];
+                if (bc != HRM_BC_TRANSMISSIVE && bc != HRM_BC_PERIODIC) return HRM_EINVAL;
+            }
+            if ((g->bc_lo[d] == HRM_BC_PERIODIC) != (g->bc_hi[d] == HRM_BC_PERIODIC)) return HRM_EINVAL;
+        }
+    }
+    for (int k = 0; k < e->nspecies; ++k) {
+        if (!(e->gamma[k] > 1.0) || !(e->cv[k] > 0.0) || !(e->pinf[k] >= 0.0)) return HRM_EINVAL;
+        if (k > 0 && e->pinf[k] != 0.0) return HRM_EINVAL;  // one stiffened gas, species 0 (Sec. 4.2)
+    }
+    if (g->precision != HRM_FP64 && g->precision != HRM_FP32) return HRM_EINVAL;
+    if (g->weights != HRM_WEIGHTS_IS) return HRM_EUNSUPPORTED;
+    if (g->precision != HRM_FP64) return HRM_EUNSUPPORTED;
+
+    hrm_ctx* c = new (std::nothrow) hrm_ctx;
+    if (!c) return HRM_ENOMEM;
+    memset(c, 0, sizeof(*c));
+    c->N = e->nspecies;
+    c->D = g->dim;
+    c->M = 2 * c->N + c->D;
+    for (int d = 0; d < 3; ++d) {
+        c->n[d] = g->n[d];
+        c->dx[d] = d < g->dim ? g->dx[d] : 1.0;
+        c->bclo[d] = d < g->dim ? g->bc_lo[d] : HRM_BC_TRANSMISSIVE;
+        c->bchi[d] = d < g->dim ? g->bc_hi[d] : HRM_BC_TRANSMISSIVE;
+    }
+    c->precision = g->precision;
+    c->weights = g->weights;
+    c->flags = g->flags;
+    c->ncell = (long long)g->n[0] * g->n[1] * g->n[2];
+    if (!((c->N == 2 || c->N == 3))) {
+        delete c;
+        return HRM_EUNSUPPORTED;
+    }
+    for (int k = 0; k < hrm::MAXN; ++k) {
+        const bool on = k < c->N;
+        c->eos.g[k] = on ? e->gamma[k] : 2.0;
+        c->eos.cv[k] = on ? e->cv[k] : 1.0;
+        c->eos.pinf[k] = on ? e->pinf[k] : 0.0;
+        c->eos.q[k] = on ? e->q[k] : 0.0;
+        c->eos.ig1[k] = 1.0 / (c->eos.g[k] - 1.0);
+        c->eos.gpi1[k] = c->eos.g[k] * c->eos.pinf[k] / (c->eos.g[k] - 1.0);
+        c->eos.cp[k] = c->eos.g[k] * c->eos.cv[k];
+    }
+    hrm_params p;
+    if (prm)
+        p = *prm;
+    else
+        hrm_default_params(&p);
+    hrm::ParDev& P = c->par;
+    P.eps_weno = p.eps_weno;
+    P.eps_i_ar = p.eps_i_ar;
+    P.eps_i_a = p.eps_i_a;
+    P.hs_i_ar = p.hs_i_ar;
+    P.hs_i_a = p.hs_i_a;
+    P.hs_i_rc2 = p.hs_i_rc2;
+    P.eps_f_ar = p.eps_f_ar;
+    P.eps_f_a = p.eps_f_a;
+    P.eps_f_re = p.eps_f_re;
+    P.hs_f_ar = p.hs_f_ar;
+    P.hs_f_a = p.hs_f_a;
+    P.hs_f_re = p.hs_f_re;
+    P.Cs = p.Cs;
+    P.qexp = p.qexp;
+    P.psi = p.psi;
+    P.hcs_a = 75.0 * p.psi / 128.0 - 37.0 / 60.0;
+    P.hcs_b = 25.0 * p.psi / 256.0 - 2.0 / 15.0;
+    P.hcs_c = 3.0 * p.psi / 256.0 - 1.0 / 60.0;
+    P.flags = g->flags;
+
+    const size_t bytes = sizeof(double) * (size_t)c->M * (size_t)c->ncell;
+    c->npart = (int)std::min<long long>((c->ncell + 255) / 256, 2048);
+    bool ok = true;
+    if (c->D > 1) ok = ok && hipMalloc((void**)&c->d_rhs, bytes) == hipSuccess;
+    ok = ok && hipMalloc((void**)&c->d_W1, bytes) == hipSuccess;
+    ok = ok && hipMalloc((void**)&c->d_W2, bytes) == hipSuccess;
+    ok = ok && hipMalloc((void**)&c->d_part, sizeof(double) * 3 * (size_t)c->npart) == hipSuccess;
+    ok = ok && hipMalloc((void**)&c->d_maxs, sizeof(double) * 4) == hipSuccess;
+    ok = ok && hipMalloc((void**)&c->d_cnt, sizeof(unsigned long long) * 8) == hipSuccess;
+    if (ok) ok = hipMemset(c->d_cnt, 0, sizeof(unsigned long long) * 8) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        hrm_destroy(c);
+        return HRM_ENOMEM;
+    }
+    *out = c;
+    return HRM_OK;
+}
+
+int hrm_destroy(hrm_ctx* c)
+{
+    if (!c) return HRM_EINVAL;
+    (void)hipDeviceSynchronize();
+    if (c->pool_ready)
+        for (int i = 0; i < 4096; ++i) {
+            (void)hipEventDestroy(c->pool[i][0]);
+            (void)hipEventDestroy(c->pool[i][1]);
+        }
+    (void)hipFree(c->d_rhs);
+    (void)hipFree(c->d_W1);
+    (void)hipFree(c->d_W2);
+    (void)hipFree(c->d_part);
+    (void)hipFree(c->d_maxs);
+    (void)hipFree(c->d_cnt);
+    delete c;
+    return HRM_OK;
+}
+
+int hrm_max_wavespeed(hrm_ctx* c, const double* d_W, double* d_out, void* stream)
+{
+    if (!c) return HRM_EINVAL;
+    if (!valid_ptr(d_W) || !valid_ptr(d_out)) return fail(c, HRM_EINVAL, "hrm_max_wavespeed: NULL pointer%s", "");
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    const int rc = dispatch(c, [&](auto ops) { decltype(ops)::wavespeed(c, d_W, d_out, s); });
+    return rc != HRM_OK ? rc : check_launch(c, "hrm_max_wavespeed");
+}
+
+int hrm_compute_dt(hrm_ctx* c, const double* d_maxspeed, double cfl, double dt_fixed, double t_end, double* d_slot,
+                   void* stream)
+{
+    if (!c) return HRM_EINVAL;
+    if (!valid_ptr(d_maxspeed) || !valid_ptr(d_slot)) return fail(c, HRM_EINVAL, "hrm_compute_dt: NULL pointer%s");
+    if (!(dt_fixed > 0.0) && !(cfl > 0.0)) return fail(c, HRM_EINVAL, "hrm_compute_dt: need cfl > 0 or dt_fixed > 0%s");
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    TimerScope t(c, HRM_T_DT, s);
+    hipLaunchKernelGGL(hrm::k_dt, dim3(1), dim3(64), 0, s, d_maxspeed, c->D, c->dx[0], c->dx[1], c->dx[2], cfl,
+                       dt_fixed, t_end, d_slot);
+    return check_launch(c, "hrm_compute_dt");
+}
+
+int hrm_rhs(hrm_ctx* c, const double* d_W, double* d_L, const double* d_slot, void* stream)
+{
+    if (!c) return HRM_EINVAL;
+    if (!valid_ptr(d_W) || !valid_ptr(d_L) || !valid_ptr(d_slot)) return fail(c, HRM_EINVAL, "hrm_rhs: NULL pointer%s");
+    if ((const double*)d_L == d_W) return fail(c, HRM_EINVAL, "hrm_rhs: d_L aliases d_W%s");
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    return run_operator(c, d_W, nullptr, nullptr, d_L, d_slot, false, 0.0, 0.0, 0, s);
+}
+
+int hrm_rk_stage(hrm_ctx* c, int stage, const double* d_Wn, const double* d_Ws, double* d_Wout, const double* d_slot,
+                 void* stream)
+{
+    static const double RK_A[3] = {0.0, 3.0 / 4.0, 1.0 / 3.0};
+    static const double RK_B[3] = {1.0, 1.0 / 4.0, 2.0 / 3.0};
+    if (!c) return HRM_EINVAL;
+    if (stage < 0 || stage > 2) return fail(c, HRM_EINVAL, "hrm_rk_stage: stage %s%lld not in 0..2", "", stage);
+    if (!valid_ptr(d_Wn) || !valid_ptr(d_Ws) || !valid_ptr(d_Wout) || !valid_ptr(d_slot))
+        return fail(c, HRM_EINVAL, "hrm_rk_stage: NULL pointer%s");
+    if ((const double*)d_Wout == d_Ws) return fail(c, HRM_EINVAL, "hrm_rk_stage: d_Wout aliases d_Ws%s");
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    return run_operator(c, d_Ws, d_Wn, d_Wout, c->d_rhs, d_slot, true, RK_A[stage], RK_B[stage],
+                        (c->flags & HRM_FUSE_RELAX) ? 1 : 0, s);
+}
+
+int hrm_relax(hrm_ctx* c, double* d_W, void* stream)
+{
+    if (!c) return HRM_EINVAL;
+    if (!valid_ptr(d_W)) return fail(c, HRM_EINVAL, "hrm_relax: NULL pointer%s");
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    const int rc = dispatch(c, [&](auto ops) { decltype(ops)::relax(c, d_W, s); });
+    return rc != HRM_OK ? rc : check_launch(c, "hrm_relax");
+}
+
+int hrm_step(hrm_ctx* c, double* d_W, double cfl, double dt_fixed, double t_end, double* d_slot, void* stream)
+{
+    static const double RK_A[3] = {0.0, 3.0 / 4.0, 1.0 / 3.0};
+    static const double RK_B[3] = {1.0, 1.0 / 4.0, 2.0 / 3.0};
+    if (!c) return HRM_EINVAL;
+    if (!valid_ptr(d_W) || !valid_ptr(d_slot)) return fail(c, HRM_EINVAL, "hrm_step: NULL pointer%s");
+    hipStream_t s = (hipStream_t)stream;
+    int rc = hrm_max_wavespeed(c, d_W, c->d_maxs, stream);
+    if (rc == HRM_OK) rc = hrm_compute_dt(c, c->d_maxs, cfl, dt_fixed, t_end, d_slot, stream);
+    if (rc == HRM_OK) rc = run_operator(c, d_W, d_W, c->d_W1, c->d_rhs, d_slot, true, RK_A[0], RK_B[0], 1, s);
+    if (rc == HRM_OK) rc = run_operator(c, c->d_W1, d_W, c->d_W2, c->d_rhs, d_slot, true, RK_A[1], RK_B[1], 1, s);
+    if (rc == HRM_OK) rc = run_operator(c, c->d_W2, d_W, d_W, c->d_rhs, d_slot, true, RK_A[2], RK_B[2], 1, s);
+    return rc;
+}
+
+int hrm_get_diagnostics(hrm_ctx* c, hrm_diag* out)
+{
+    if (!c || !out) return HRM_EINVAL;
+    if (hipStreamSynchronize(c->last_stream) != hipSuccess ||
+        hipMemcpy(out, c->d_cnt, sizeof(hrm_diag), hipMemcpyDeviceToHost) != hipSuccess) {
+        snprintf(c->err, sizeof(c->err), "hrm_get_diagnostics: %s", hipGetErrorString(hipGetLastError()));
+        return HRM_EDEVICE;
+    }
+    return out->relax_bad ? HRM_EADMISSIBLE : HRM_OK;
+}
+
+int hrm_reset_diagnostics(hrm_ctx* c, void* stream)
+{
+    if (!c) return HRM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    hipLaunchKernelGGL(hrm::k_zero_u64, dim3(1), dim3(64), 0, s, c->d_cnt, 8);
+    return check_launch(c, "hrm_reset_diagnostics");
+}
+
+int hrm_set_timing(hrm_ctx* c, int mask)
+{
+    if (!c) return HRM_EINVAL;
+    if (mask && !c->pool_ready) {
+        for (int i = 0; i < 4096; ++i)
+            if (hipEventCreate(&c->pool[i][0]) != hipSuccess || hipEventCreate(&c->pool[i][1]) != hipSuccess) {
+                snprintf(c->err, sizeof(c->err), "hrm_set_timing: %s", hipGetErrorString(hipGetLastError()));
+                return HRM_EDEVICE;
+            }
+        c->pool_ready = 1;
+    }
+    c->timing_mask = mask;
+    return HRM_OK;
+}
+
+int hrm_get_timing(hrm_ctx* c, double* ms, long long* counts)
+{
+    if (!c || !ms || !counts) return HRM_EINVAL;
+    if (hipStreamSynchronize(c->last_stream) != hipSuccess) {
+        snprintf(c->err, sizeof(c->err), "hrm_get_timing: %s", hipGetErrorString(hipGetLastError()));
+        return HRM_EDEVICE;
+    }
+    fold_timers(c);
+    for (int k = 0; k < HRM_NTIMERS; ++k) {
+        ms[k] = c->tms[k];
+        counts[k] = c->tcnt[k];
+        c->tms[k] = 0.0;
+        c->tcnt[k] = 0;
+    }
+    return HRM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,490 @@
+// hrm_device.hpp -- gfx950 device arithmetic of the hot path: mixture EOS,
+// characteristic projection, incremental-stencil WENO, HLLC, HCS
+// reconstruction with shock-sensor blending, the positivity-preserving
+// interpolation and flux limiters, and the infinite-rate thermal relaxation
+// (Wong, Angel & Kiris, arXiv:2208.04488, Sec. 2, Sec. 4, App. C, App. D).
+//
+// Everything here is double precision.  Component slots of a conservative
+// vector W (Sec. 2): alpha_k rho_k (k < N), rho u_d (d < D), E, alpha_k (k < N-1).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace hrm {
+
+constexpr int MAXN = 8;
+
+// grid flags (mirror of the public header)
+constexpr int F_NO_LIMITERS = 1;
+constexpr int F_NO_BLEND = 2;
+constexpr int F_FIRST_ORDER = 4;
+
+// species table with the derived constants every kernel needs
+struct EosDev {
+    double g[MAXN], cv[MAXN], pinf[MAXN], q[MAXN];
+    double ig1[MAXN];   // 1/(gamma_k - 1)
+    double gpi1[MAXN];  // gamma_k pinf_k/(gamma_k - 1)
+    double cp[MAXN];    // gamma_k c_v,k
+};
+
+struct ParDev {
+    double eps_weno;
+    double eps_i_ar, eps_i_a, hs_i_ar, hs_i_a, hs_i_rc2;
+    double eps_f_ar, eps_f_a, eps_f_re, hs_f_ar, hs_f_a, hs_f_re;
+    double Cs, qexp, psi;
+    double hcs_a, hcs_b, hcs_c;  // eq:reconstructed_G coefficients from psi
+    int flags;
+};
+
+// counters accumulated per thread, flushed once per wave
+enum { C_ALG1 = 0, C_ALG2, C_IHS, C_ALG3, C_ALG4, C_FHS, C_RELAX_BAD, C_N };
+
+// A full state: conservative and primitive slots side by side.
+template <int N, int D>
+struct St {
+    double ar[N];   // alpha_k rho_k
+    double mom[D];  // rho u_d
+    double u[D];
+    double p, E;
+    double al[N];   // all N volume fractions, al[N-1] = 1 - sum of the others
+    double rho, c, rc2;
+};
+
+// Sec. 2 mixture EOS: Gam = 1/(gbar-1) = sum alpha_k/(gamma_k-1),
+// Pi = gbar pbar/(gbar-1) = sum alpha_k gamma_k pinf_k/(gamma_k-1);
+// rho(e - qbar) = Gam p + Pi; rho c^2 = gbar (p + pbar) = p + (p + Pi)/Gam.
+template <int N>
+__device__ inline void mixture(const EosDev& e, const double* al, double& Gam, double& Pi)
+{
+    Gam = 0.0;
+    Pi = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        Gam += al[k] * e.ig1[k];
+        Pi += al[k] * e.gpi1[k];
+    }
+}
+
+// conservative W[M] -> full state (hot-path step a1)
+template <int N, int D>
+__device__ inline void state_from_W(const EosDev& e, const double* W, St<N, D>& s)
+{
+    constexpr int IE = N + D, IA = N + D + 1;
+    double rho = 0.0, rq = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        s.ar[k] = W[k];
+        rho += W[k];
+        rq += W[k] * e.q[k];
+    }
+    double asum = 0.0;
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) {
+        s.al[k] = W[IA + k];
+        asum += W[IA + k];
+    }
+    s.al[N - 1] = 1.0 - asum;
+    const double irho = 1.0 / rho;
+    double m2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        s.mom[d] = W[N + d];
+        s.u[d] = W[N + d] * irho;
+        m2 += W[N + d] * W[N + d];
+    }
+    double Gam, Pi;
+    mixture<N>(e, s.al, Gam, Pi);
+    const double iG = 1.0 / Gam;
+    s.E = W[IE];
+    const double re = W[IE] - 0.5 * m2 * irho - rq;
+    s.p = (re - Pi) * iG;
+    s.rc2 = s.p + (s.p + Pi) * iG;
+    s.rho = rho;
+    s.c = sqrt(s.rc2 * irho);
+}
+
+// primitive slots (ar, u, p, al[0..N-2]) already set -> the rest of the state
+template <int N, int D>
+__device__ inline void complete_from_prim(const EosDev& e, St<N, D>& s)
+{
+    double rho = 0.0, rq = 0.0, asum = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        rho += s.ar[k];
+        rq += s.ar[k] * e.q[k];
+    }
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) asum += s.al[k];
+    s.al[N - 1] = 1.0 - asum;
+    double Gam, Pi;
+    mixture<N>(e, s.al, Gam, Pi);
+    double u2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        s.mom[d] = rho * s.u[d];
+        u2 += s.u[d] * s.u[d];
+    }
+    s.rho = rho;
+    s.E = Gam * s.p + Pi + 0.5 * rho * u2 + rq;
+    s.rc2 = s.p + (s.p + Pi) / Gam;
+    s.c = sqrt(s.rc2 / rho);
+}
+
+// rho(e - qbar) of a conservative vector
+template <int N, int D>
+__device__ inline double rhoe_tilde(const EosDev& e, const double* W)
+{
+    double rho = 0.0, rq = 0.0, m2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        rho += W[k];
+        rq += W[k] * e.q[k];
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) m2 += W[N + d] * W[N + d];
+    return W[N + D] - 0.5 * m2 / rho - rq;
+}
+
+// App. C incremental-stencil WENO, left-biased at i+1/2 from u_{i-2..i+2}.
+// The four unnormalised weights are scaled by the common product of the
+// denominators so the weighting needs one division instead of six.
+__device__ inline double weno_is(double um2, double um1, double u0, double up1, double up2, double eps)
+{
+    const double s0 = 0.5 * (u0 + up1);
+    const double s1 = 0.5 * (3.0 * u0 - um1);
+    const double s2 = 0.125 * (3.0 * u0 + 6.0 * up1 - up2);
+    const double s3 = 0.125 * (3.0 * um2 - 10.0 * um1 + 15.0 * u0);
+    const double a0 = u0 - up1, a1 = um1 - u0;
+    const double b01a = um1 - 2.0 * u0 + up1, b01b = um1 - up1;
+    const double b2a = u0 - 2.0 * up1 + up2, b2b = 3.0 * u0 - 4.0 * up1 + up2;
+    const double b3a = um2 - 2.0 * um1 + u0, b3b = um2 - 4.0 * um1 + 3.0 * u0;
+    const double t5a = up2 - 4.0 * up1 + 6.0 * u0 - 4.0 * um1 + um2;
+    const double t5b = up2 - 2.0 * up1 + 2.0 * um1 - um2;
+    constexpr double c13 = 13.0 / 12.0;
+    const double B0 = a0 * a0 + eps;
+    const double B1 = a1 * a1 + eps;
+    const double B01 = c13 * b01a * b01a + 0.25 * b01b * b01b + eps;
+    const double B2 = c13 * b2a * b2a + 0.25 * b2b * b2b + eps;
+    const double B3 = c13 * b3a * b3a + 0.25 * b3b * b3b + eps;
+    const double tau = c13 * t5a * t5a + 0.25 * t5b * t5b;
+    // eta_k times Q = B0 B1 B01 B2 B3
+    const double t2 = tau * tau;
+    const double B23 = B2 * B3, B0B1 = B0 * B1;
+    const double e0 = (15.0 / 32.0) * (B0 * B01 + t2) * B1 * B23;
+    const double e1 = (5.0 / 32.0) * (B1 * B01 + t2) * B0 * B23;
+    const double e2 = (5.0 / 16.0) * (B2 + tau) * B0B1 * B01 * B3;
+    const double e3 = (1.0 / 16.0) * (B3 + tau) * B0B1 * B01 * B2;
+    return (e0 * s0 + e1 * s1 + e2 * s2 + e3 * s3) / (e0 + e1 + e2 + e3);
+}
+
+// Sec. 4.1.1 HLLC for the five-equation model in direction DIR.  Writes
+// G = F^HLLC + (0, ..., f_alpha) and returns s_*.  sign(0) = 0.
+template <int N, int D, int DIR>
+__device__ inline double hllc(const St<N, D>& L, const St<N, D>& R, double* G)
+{
+    constexpr int IE = N + D, IA = N + D + 1;
+    const double uL = L.u[DIR], uR = R.u[DIR];
+    const double ub = 0.5 * (uL + uR), cb = 0.5 * (L.c + R.c);
+    const double sL = fmin(ub - cb, uL - L.c);
+    const double sR = fmax(ub + cb, uR + R.c);
+    const double dL = sL - uL, dR = sR - uR;
+    const double ss = (R.p - L.p + L.rho * uL * dL - R.rho * uR * dR) / (L.rho * dL - R.rho * dR);
+    const double sg = ss > 0.0 ? 1.0 : (ss < 0.0 ? -1.0 : 0.0);
+    const double wl = 0.5 * (1.0 + sg), wr = 0.5 * (1.0 - sg);
+    const double sm = fmin(0.0, sL), sp = fmax(0.0, sR);
+    const double chiL = dL / (sL - ss), chiR = dR / (sR - ss);
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        G[k] = wl * (L.ar[k] * uL + sm * (chiL * L.ar[k] - L.ar[k])) +
+               wr * (R.ar[k] * uR + sp * (chiR * R.ar[k] - R.ar[k]));
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const double FLd = L.mom[d] * uL + (d == DIR ? L.p : 0.0);
+        const double FRd = R.mom[d] * uR + (d == DIR ? R.p : 0.0);
+        const double WsL = d == DIR ? chiL * L.rho * ss : chiL * L.rho * L.u[d];
+        const double WsR = d == DIR ? chiR * R.rho * ss : chiR * R.rho * R.u[d];
+        G[N + d] = wl * (FLd + sm * (WsL - L.mom[d])) + wr * (FRd + sp * (WsR - R.mom[d]));
+    }
+    {
+        const double EsL = chiL * (L.E + (ss - uL) * (L.rho * ss + L.p / dL));
+        const double EsR = chiR * (R.E + (ss - uR) * (R.rho * ss + R.p / dR));
+        G[IE] = wl * ((L.E + L.p) * uL + sm * (EsL - L.E)) + wr * ((R.E + R.p) * uR + sp * (EsR - R.E));
+    }
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) G[IA + k] = wl * (L.al[k] * ss) + wr * (R.al[k] * ss);
+    return ss;
+}
+
+// theta solving (1-theta) a + theta b = min(eps, a) when b < min(eps, a); else 1
+__device__ inline double lim_theta(double a, double b, double eps)
+{
+    const double m = fmin(eps, a);
+    return b < m ? (a - m) / (a - b) : 1.0;
+}
+
+// Sec. 4.3.2 interpolation limiter on an interpolated primitive state V
+// (partial densities and volume fractions are blended toward the node state;
+// velocity and pressure are kept), then the hard switch to the node state.
+template <int N, int D>
+__device__ inline void interp_limit(const EosDev& e, const ParDev& P, St<N, D>& V, const St<N, D>& node,
+                                    unsigned* cnt)
+{
+#pragma unroll
+    for (int k = 0; k < N; ++k) {  // Alg. 1
+        const double a = node.ar[k], b = V.ar[k];
+        const double m = fmin(P.eps_i_ar, a);
+        if (b < m) {
+            const double th = (a - m) / (a - b);
+            V.ar[k] = (1.0 - th) * a + th * b;
+            cnt[C_ALG1]++;
+        }
+    }
+    double at[N], asum = 0.0;  // Alg. 2
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) {
+        at[k] = V.al[k];
+        asum += at[k];
+    }
+    at[N - 1] = 1.0 - asum;
+    double th = 1.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) th = fmin(th, lim_theta(node.al[k], at[k], P.eps_i_a));
+    if (th < 1.0) {
+#pragma unroll
+        for (int k = 0; k < N - 1; ++k) V.al[k] = (1.0 - th) * node.al[k] + th * V.al[k];
+        cnt[C_ALG2]++;
+    }
+    // hard switch
+    double al[N];
+    asum = 0.0;
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) {
+        al[k] = V.al[k];
+        asum += al[k];
+    }
+    al[N - 1] = 1.0 - asum;
+    double Gam, Pi;
+    mixture<N>(e, al, Gam, Pi);
+    const double rc2 = V.p + (V.p + Pi) / Gam;
+    bool hs = !isfinite(rc2) || !isfinite(V.p);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        hs |= !isfinite(V.ar[k]) || !isfinite(al[k]);
+        hs |= V.ar[k] < fmin(P.hs_i_ar, node.ar[k]);
+        hs |= al[k] < fmin(P.hs_i_a, node.al[k]);
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) hs |= !isfinite(V.u[d]);
+    hs |= rc2 < fmin(P.hs_i_rc2, node.rc2);
+    if (hs) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) V.ar[k] = node.ar[k];
+#pragma unroll
+        for (int d = 0; d < D; ++d) V.u[d] = node.u[d];
+        V.p = node.p;
+#pragma unroll
+        for (int k = 0; k < N - 1; ++k) V.al[k] = node.al[k];
+        cnt[C_IHS]++;
+    }
+}
+
+// all N volume fractions of a conservative vector
+template <int N, int D>
+__device__ inline void alphas(const double* W, double* al)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) {
+        al[k] = W[N + D + 1 + k];
+        s += al[k];
+    }
+    al[N - 1] = 1.0 - s;
+}
+
+// Sec. 4.3.2 flux limiter (Alg. 3, Alg. 4, hard switch) at the face between
+// nodes L = i and R = i+1.  G pairs are given as the "-" vector (M slots)
+// plus the alpha slots of the "+" vector (N-1); the other slots agree.
+//   W_i^+     = W_i     - 2 lambda (G^- - F_i)
+//   W_{i+1}^- = W_{i+1} + 2 lambda (G^+ - F_{i+1})
+template <int N, int D, int DIR>
+__device__ inline void flux_limit(const EosDev& e, const ParDev& P, const St<N, D>& L, const St<N, D>& R,
+                                  double lam, const double* Gho, const double* Gho_p, const double* Glo,
+                                  const double* Glo_p, double* G, double* Gp, unsigned* cnt)
+{
+    constexpr int M = 2 * N + D, IE = N + D, IA = N + D + 1;
+    double WL[M], WR[M], FL[M], FR[M];
+    const double uL = L.u[DIR], uR = R.u[DIR];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        WL[k] = L.ar[k];
+        WR[k] = R.ar[k];
+        FL[k] = L.ar[k] * uL;
+        FR[k] = R.ar[k] * uR;
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        WL[N + d] = L.mom[d];
+        WR[N + d] = R.mom[d];
+        FL[N + d] = L.mom[d] * uL + (d == DIR ? L.p : 0.0);
+        FR[N + d] = R.mom[d] * uR + (d == DIR ? R.p : 0.0);
+    }
+    WL[IE] = L.E;
+    WR[IE] = R.E;
+    FL[IE] = (L.E + L.p) * uL;
+    FR[IE] = (R.E + R.p) * uR;
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) {
+        WL[IA + k] = L.al[k];
+        WR[IA + k] = R.al[k];
+        FL[IA + k] = 0.0;
+        FR[IA + k] = 0.0;
+    }
+    const double l2 = 2.0 * lam;
+    // half-cell states of the first-order pair (reference values)
+    double Wp_lo[M], Wm_lo[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        const double gp = c >= IA ? Glo_p[c - IA] : Glo[c];
+        Wp_lo[c] = WL[c] - l2 * (Glo[c] - FL[c]);
+        Wm_lo[c] = WR[c] + l2 * (gp - FR[c]);
+    }
+    double ap_lo[N], am_lo[N];
+    alphas<N, D>(Wp_lo, ap_lo);
+    alphas<N, D>(Wm_lo, am_lo);
+    const double rep_lo = rhoe_tilde<N, D>(e, Wp_lo), rem_lo = rhoe_tilde<N, D>(e, Wm_lo);
+
+    // Alg. 3
+    double Wp[M], Wm[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        const double gp = c >= IA ? Gho_p[c - IA] : Gho[c];
+        Wp[c] = WL[c] - l2 * (Gho[c] - FL[c]);
+        Wm[c] = WR[c] + l2 * (gp - FR[c]);
+    }
+    double th = 1.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        th = fmin(th, lim_theta(Wp_lo[k], Wp[k], P.eps_f_ar));
+        th = fmin(th, lim_theta(Wm_lo[k], Wm[k], P.eps_f_ar));
+    }
+    {
+        double ap[N], am[N];
+        alphas<N, D>(Wp, ap);
+        alphas<N, D>(Wm, am);
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            th = fmin(th, lim_theta(ap_lo[k], ap[k], P.eps_f_a));
+            th = fmin(th, lim_theta(am_lo[k], am[k], P.eps_f_a));
+        }
+    }
+    if (th < 1.0) cnt[C_ALG3]++;
+    double Gs[M], Gsp[N > 1 ? N - 1 : 1];
+#pragma unroll
+    for (int c = 0; c < M; ++c) Gs[c] = (1.0 - th) * Glo[c] + th * Gho[c];
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) Gsp[k] = (1.0 - th) * Glo_p[k] + th * Gho_p[k];
+
+    // Alg. 4
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        const double gp = c >= IA ? Gsp[c - IA] : Gs[c];
+        Wp[c] = WL[c] - l2 * (Gs[c] - FL[c]);
+        Wm[c] = WR[c] + l2 * (gp - FR[c]);
+    }
+    const double th2 = fmin(lim_theta(rep_lo, rhoe_tilde<N, D>(e, Wp), P.eps_f_re),
+                            lim_theta(rem_lo, rhoe_tilde<N, D>(e, Wm), P.eps_f_re));
+    if (th2 < 1.0) cnt[C_ALG4]++;
+#pragma unroll
+    for (int c = 0; c < M; ++c) G[c] = (1.0 - th2) * Glo[c] + th2 * Gs[c];
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) Gp[k] = (1.0 - th2) * Glo_p[k] + th2 * Gsp[k];
+
+    // hard switch on the final half-cell states
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        const double gp = c >= IA ? Gp[c - IA] : G[c];
+        Wp[c] = WL[c] - l2 * (G[c] - FL[c]);
+        Wm[c] = WR[c] + l2 * (gp - FR[c]);
+    }
+    bool hs = false;
+#pragma unroll
+    for (int c = 0; c < M; ++c) hs |= !isfinite(G[c]);
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) hs |= !isfinite(Gp[k]);
+    double ap[N], am[N];
+    alphas<N, D>(Wp, ap);
+    alphas<N, D>(Wm, am);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        hs |= Wp[k] < fmin(P.hs_f_ar, Wp_lo[k]);
+        hs |= Wm[k] < fmin(P.hs_f_ar, Wm_lo[k]);
+        hs |= ap[k] < fmin(P.hs_f_a, ap_lo[k]);
+        hs |= am[k] < fmin(P.hs_f_a, am_lo[k]);
+    }
+    const double rep = rhoe_tilde<N, D>(e, Wp), rem = rhoe_tilde<N, D>(e, Wm);
+    hs |= !isfinite(rep) || !isfinite(rem);
+    hs |= rep < fmin(P.hs_f_re, rep_lo);
+    hs |= rem < fmin(P.hs_f_re, rem_lo);
+    if (hs) {
+        cnt[C_FHS]++;
+#pragma unroll
+        for (int c = 0; c < M; ++c) G[c] = Glo[c];
+#pragma unroll
+        for (int k = 0; k < N - 1; ++k) Gp[k] = Glo_p[k];
+    }
+}
+
+// normalised fourth-order second derivative of the shock sensor (Sec. 4.3.1)
+__device__ inline double sensor_ratio(double v0, double v1, double v2, double v3, double v4)
+{
+    const double num = fabs(-v0 + 16.0 * v1 - 30.0 * v2 + 16.0 * v3 - v4);
+    const double den = fabs(v0 + 16.0 * v1 + 30.0 * v2 + 16.0 * v3 + v4);
+    return den > 0.0 ? num / den : (num > 0.0 ? 1.0 : 0.0);
+}
+
+// Sec. 4.2 infinite-rate thermal relaxation of one cell (species 0 is the
+// only stiffened gas): A p^2 + B p + C = 0 (eq:Ap_Bp_Cp_1..3), positive root
+// (taken as 2C/(-B - sqrt) when B > 0), T from eq:T_relax_e, then
+// alpha_k = alpha_k rho_k / rho_k(p, T) for k < N-1.  Returns false (and leaves
+// W unchanged) when rho(e - qbar) <= 0 or no positive root exists.
+template <int N, int D>
+__device__ inline bool relax_cell(const EosDev& e, double* W)
+{
+    constexpr int IE = N + D, IA = N + D + 1;
+    double rho = 0.0, rq = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        rho += W[k];
+        rq += W[k] * e.q[k];
+    }
+    const double irho = 1.0 / rho;
+    double cvb = 0.0, cpb = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const double Y = W[k] * irho;
+        cvb += Y * e.cv[k];
+        cpb += Y * e.cp[k];
+    }
+    double m2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) m2 += W[N + d] * W[N + d];
+    const double re = W[IE] - 0.5 * m2 * irho - rq;
+    if (!(re > 0.0) || !(rho > 0.0)) return false;
+    const double Y0 = W[0] * irho;
+    const double p1 = e.pinf[0], R1 = e.cp[0] - e.cv[0];
+    const double Rg = (cpb - cvb) - Y0 * R1;
+    const double A = cvb;
+    const double B = -(re * (cpb - cvb) - p1 * cvb - p1 * Y0 * R1);
+    const double C = -re * p1 * Rg;
+    const double sq = sqrt(B * B - 4.0 * A * C);
+    const double p = B <= 0.0 ? (-B + sq) / (2.0 * A) : 2.0 * C / (-B - sq);
+    if (!(p > 0.0) || !isfinite(p)) return false;
+    const double T = re * irho / (Y0 * (p + e.g[0] * p1) * e.cv[0] / (p + p1) + cvb - Y0 * e.cv[0]);
+    if (!(T > 0.0) || !isfinite(T)) return false;
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) W[IA + k] = W[k] * ((e.g[k] - 1.0) * e.cv[k] * T) / (p + e.pinf[k]);
+    return true;
+}
+
+}  // namespace hrm

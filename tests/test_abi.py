@@ -1,0 +1,70 @@
+"""Host-side checks of the C-ABI library: it loads, exports every function the
+header declares, and its argument validation runs before any device call."""
+import ctypes
+
+import pytest
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_2208_04488_amd import hrm
+    return hrm
+
+
+def test_exports_every_declared_symbol(H):
+    names = H.header_functions()
+    assert {"hrm_create", "hrm_rk_stage", "hrm_relax", "hrm_max_wavespeed", "hrm_destroy"} <= set(names)
+    for name in names:
+        assert hasattr(H.lib, name), name
+
+
+def test_default_params_are_the_papers(H):
+    p = H.hrm_default_params()
+    assert (p.eps_weno, p.eps_i_ar, p.eps_i_a) == (1e-15, 1e-10, 1e-10)
+    assert (p.hs_i_ar, p.hs_i_a, p.hs_i_rc2) == (1e-11, 1e-11, 1e-9)
+    assert (p.eps_f_ar, p.eps_f_a, p.eps_f_re) == (1e-10, 1e-10, 1e-8)
+    assert (p.hs_f_ar, p.hs_f_a, p.hs_f_re) == (1e-11, 1e-11, 1e-9)
+    assert (p.Cs, p.qexp, p.psi) == (1e12, 2.0, 256.0 / 175.0)
+
+
+def _eos(H, pinf1=0.0):
+    return H.make_eos([4.4, 1.4], [954.5, 719.3], [6e8, pinf1], [0.0, 0.0])
+
+
+@pytest.mark.parametrize("case", ["dim0", "dim4", "n0", "unused_n", "dx0", "bc", "half_periodic", "species1",
+                                  "second_liquid", "gamma1", "precision"])
+def test_create_rejects_bad_input(H, case):
+    g = H.make_grid(2, (8, 8), (0.1, 0.1), [(0, 0), (0, 0)])
+    e = _eos(H)
+    if case == "dim0":
+        g.dim = 0
+    elif case == "dim4":
+        g.dim = 4
+    elif case == "n0":
+        g.n[1] = 0
+    elif case == "unused_n":
+        g.n[2] = 2
+    elif case == "dx0":
+        g.dx[0] = 0.0
+    elif case == "bc":
+        g.bc_lo[0] = 7
+    elif case == "half_periodic":
+        g.bc_lo[0] = H.BC_PERIODIC
+    elif case == "species1":
+        e.nspecies = 1
+    elif case == "second_liquid":
+        e = _eos(H, pinf1=1e8)
+    elif case == "gamma1":
+        e.gamma[1] = 1.0
+    elif case == "precision":
+        g.precision = 9
+    ctx = ctypes.c_void_p(123)
+    rc = H.lib.hrm_create(ctypes.byref(g), ctypes.byref(e), None, ctypes.byref(ctx))
+    assert rc == H.HRM_EINVAL
+    assert ctx.value is None
+
+
+def test_null_context_is_rejected(H):
+    assert H.lib.hrm_relax(None, None, None) == H.HRM_EINVAL
+    assert H.lib.hrm_rk_stage(None, 0, None, None, None, None, None) == H.HRM_EINVAL
+    assert H.lib.hrm_destroy(None) == H.HRM_EINVAL

@@ -1,0 +1,284 @@
+"""Parity of the HIP library (through its C-ABI) with the CPU oracle.
+
+Both sides get the same seeded inputs; every comparison is element by element.
+Tolerance: the FP64 path must agree to 1e-11 relative per step, measured per
+component as max |W_gpu - W_oracle| / scale_c with scale_c = max |W_c| for
+partial densities and energy, max(rho) * max(|u| + c) for momentum and 1 for
+volume fractions.  Diagnostic counters (limiter activations, hard switches)
+must match exactly.
+"""
+import numpy as np
+import pytest
+
+from paper_2208_04488_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2208_04488_amd import hrm
+    return hrm
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+def scales(W, N, D, cmax):
+    M = W.shape[0]
+    s = np.abs(W.reshape(M, -1)).max(axis=1)
+    rho = W[:N].sum(axis=0)
+    s[N:N + D] = max(s[N:N + D].max(), rho.max() * cmax)
+    s[N + D + 1:] = 1.0
+    return np.maximum(s, 1e-300)
+
+
+def rel_err(A, B, N, D, cmax):
+    s = scales(B, N, D, cmax)
+    M = A.shape[0]
+    return (np.abs(A - B).reshape(M, -1).max(axis=1) / s).max()
+
+
+def solver(H, prob, flags, W=None):
+    return H.Solver(prob, flags=flags, W=W)
+
+
+def check_stages(H, orc, prob, W0, flags=0, relax=True, tol=TOL, counters=True):
+    """Three SSP-RK3 stages from the same inputs on both sides."""
+    import torch
+    N, D = prob.N, prob.D
+    o = orc.from_problem(prob, flags=flags & 7)
+    dt, lam = o.dt(W0, prob.cfl)
+    cmax = o.max_wavespeed(W0).max()
+    s = solver(H, prob, (flags & 7) | (H.FUSE_RELAX if relax else 0), W=W0)
+    s.set_slot(dt, lam)
+    Wn = s.W.clone()
+    Ws = Wn
+    Wo_s = W0
+    H.hrm_reset_diagnostics(s.ctx)
+    for k in range(3):
+        ref = o.stage(k, W0, Wo_s, dt, lam, relax=relax)
+        got = s.stage(k, Wn, Ws)
+        torch.cuda.synchronize()
+        err = rel_err(got.cpu().numpy(), ref, N, D, cmax)
+        assert err <= tol, (prob.name, k, err)
+        # next stage from the oracle's output on both sides
+        Wo_s = ref
+        Ws = torch.from_numpy(ref).cuda()
+    if counters:
+        dg = s.diagnostics()
+        co = o.counter_dict()
+        for key in ("alg1", "alg2", "interp_hs", "alg3", "alg4", "flux_hs", "relax_bad"):
+            assert dg[key] == co[key], (key, dg[key], co[key])
+    s.close()
+    return o.counter_dict()
+
+
+def developed(orc, prob, steps, flags=0):
+    o = orc.from_problem(prob, flags=flags & 7)
+    W = prob.W
+    for _ in range(steps):
+        W, _ = o.step(W, cfl=prob.cfl, dt_fixed=prob.dt_fixed)
+    return W
+
+
+# ------------------------------------------------------------------ point-wise kernels
+@pytest.mark.parametrize("eos_name,D", [("table1", 1), ("three", 2), ("three", 3), ("cfgA", 2)])
+def test_relax_parity(H, orc, eos_name, D):
+    import torch
+    eos = {"table1": I.table1_eos(), "three": I.eos_of(I.LIQ_B, I.AIR, I.HELIUM),
+           "cfgA": I.eos_of(I.LIQ_A, I.AIR)}[eos_name]
+    N = eos.N
+    n = 5000
+    W = I.random_admissible(eos, D, n, seed=17 + D, p_range=(1e3, 1e11))
+    rng = np.random.default_rng(3)
+    W[:N] *= rng.uniform(0.3, 3.0, (N, n))  # off thermal equilibrium
+    prob = I.Problem("relax", eos, D, (n,) + (1,) * (D - 1), (1.0,) * D, [(0, 0)] * D,
+                     W.reshape((W.shape[0], 1, 1, n)))
+    o = orc.from_problem(prob)
+    ref = o.relax(prob.W)
+    s = solver(H, prob, 0)
+    s.relax()
+    got = s.state()
+    assert np.array_equal(got[: N + D + 1], prob.W[: N + D + 1])
+    err = np.abs(got[N + D + 1:] - ref[N + D + 1:]).max()
+    assert err <= TOL, err
+    assert s.diagnostics()["relax_bad"] == o.counters[6] == 0
+    s.close()
+
+
+def test_relax_leaves_inadmissible_cells(H, orc):
+    eos = I.table1_eos()
+    W = I.random_admissible(eos, 1, 64, seed=5).reshape(5, 1, 1, 64)
+    W[3, 0, 0, 7] = W[0, 0, 0, 7] * eos.q[0] - 10.0  # rho(e - qbar) < 0
+    W[3, 0, 0, 9] = np.nan
+    prob = I.Problem("bad", eos, 1, (64,), (1.0,), [(0, 0)], W)
+    s = solver(H, prob, 0)
+    s.relax()
+    got = s.state()
+    assert np.array_equal(got[:, 0, 0, 7], W[:, 0, 0, 7])
+    assert s.diagnostics()["relax_bad"] == 2
+    s.close()
+
+
+@pytest.mark.parametrize("maker", ["config1", "shock_tube_extreme", "advection_2d", "config2_small", "config3_small"])
+def test_wavespeed_and_dt_parity(H, orc, maker):
+    prob = {"config1": lambda: I.config1(400), "shock_tube_extreme": lambda: I.shock_tube(1000, True),
+            "advection_2d": lambda: I.advection_2d(32), "config2_small": lambda: I.config2(96, 48),
+            "config3_small": lambda: I.config3(20)}[maker]()
+    o = orc.from_problem(prob)
+    s = solver(H, prob, H.FUSE_RELAX)
+    ms = s.wavespeed()
+    ref = o.max_wavespeed(prob.W)
+    assert np.allclose(ms, ref, rtol=1e-13, atol=0)
+    dt, lam, t = s.compute_dt(prob.cfl, prob.dt_fixed)
+    dto, lamo = o.dt(prob.W, prob.cfl, prob.dt_fixed)
+    assert dt == pytest.approx(dto, rel=1e-13)
+    assert np.allclose(lam, lamo, rtol=1e-13)
+    s.close()
+
+
+# ------------------------------------------------------------------ the stage
+CASES = {
+    "config1": lambda orc: (I.config1(400), None),
+    "config1_developed": lambda orc: (I.config1(400), 40),
+    "shock_tube_extreme": lambda orc: (I.shock_tube(1000, True), 15),
+    "advection_2d": lambda orc: (I.advection_2d(32), None),
+    "interface_advection": lambda orc: (I.interface_advection(500), 20),
+    "config2_small": lambda orc: (I.config2(128, 64), 4),
+    "config2_ragged": lambda orc: (I.config2(100, 37), 2),
+    "config3_small": lambda orc: (I.config3(24), None),
+    "config3_ragged": lambda orc: (I.config3(20), 1),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_stage_parity(H, orc, name):
+    prob, steps = CASES[name](orc)
+    W0 = prob.W if steps is None else developed(orc, prob, steps)
+    check_stages(H, orc, prob, W0)
+
+
+@pytest.mark.parametrize("flags", [1, 2, 4])
+def test_stage_parity_flags(H, orc, flags):
+    prob = I.shock_tube(400, True)
+    W0 = developed(orc, prob, 10, flags=0)
+    check_stages(H, orc, prob, W0, flags=flags, counters=flags != 1)
+
+
+def test_stage_parity_without_relaxation(H, orc):
+    prob = I.config2(64, 40)
+    check_stages(H, orc, prob, developed(orc, prob, 2), relax=False)
+
+
+def rough_problem(D, n, seed):
+    """Every cell an independent admissible state: jumps everywhere, so the
+    limiters and hard switches fire on many faces."""
+    eos = I.eos_of(I.LIQ_B, I.AIR, I.HELIUM)
+    cells = int(np.prod(n))
+    W = I.random_admissible(eos, D, cells, seed=seed, p_range=(1e3, 1e10), u_scale=500.0, mixed=False)
+    nn = tuple(n) + (1,) * (3 - D)
+    W = W.reshape((W.shape[0], nn[2], nn[1], nn[0]))
+    dx = tuple(1e-3 for _ in range(D))
+    return I.Problem("rough", eos, D, tuple(n), dx, [(0, 0)] * D, np.ascontiguousarray(W))
+
+
+@pytest.mark.parametrize("D,n", [(1, (300,)), (2, (40, 33)), (3, (12, 11, 10))])
+def test_stage_parity_rough(H, orc, D, n):
+    prob = rough_problem(D, n, seed=100 + D)
+    cnt = check_stages(H, orc, prob, prob.W)
+    assert cnt["alg1"] + cnt["alg2"] + cnt["interp_hs"] > 0
+    assert cnt["alg3"] > 0
+
+
+@pytest.mark.parametrize("n,bc", [(1, 0), (2, 0), (3, 0), (5, 0), (3, 1), (4, 1), (7, 1), (255, 0), (256, 1),
+                                  (511, 0)])
+def test_stage_parity_small_and_edge_sizes(H, orc, n, bc):
+    prob = I.config1(n) if bc == 0 else I.interface_advection(n)
+    if bc == 0:
+        prob.W = developed(orc, prob, 3) if n >= 5 else prob.W
+    check_stages(H, orc, prob, prob.W)
+
+
+def test_full_step_parity_and_rhs(H, orc):
+    import torch
+    prob = I.config2(128, 64)
+    W0 = developed(orc, prob, 3)
+    o = orc.from_problem(prob)
+    cmax = o.max_wavespeed(W0).max()
+    dt, lam = o.dt(W0, prob.cfl)
+    s = solver(H, prob, H.FUSE_RELAX, W=W0)
+    s.set_slot(dt, lam)
+    L = s.rhs().cpu().numpy()
+    Lo = o.rhs(W0, lam)
+    errL = (np.abs(dt * (L - Lo)).reshape(prob.M, -1).max(axis=1) / scales(W0, prob.N, prob.D, cmax)).max()
+    assert errL <= TOL, errL
+    s.set_slot(0.0, [0.0, 0.0])
+    s.step(cfl=prob.cfl)
+    ref, dto = o.step(W0, cfl=prob.cfl)
+    torch.cuda.synchronize()
+    assert s.slot[0].item() == pytest.approx(dto, rel=1e-13)
+    assert rel_err(s.state(), ref, prob.N, prob.D, cmax) <= TOL
+    s.close()
+
+
+def test_full_size_bench_workload_step(H, orc):
+    """The benchmark's workload at its full size (1024 x 512, three species):
+    one RK3 step in the benchmark's launch configuration (hrm_step), every
+    cell compared with the oracle."""
+    import torch
+    prob = I.config2()
+    o = orc.from_problem(prob)
+    cmax = o.max_wavespeed(prob.W).max()
+    ref, dto = o.step(prob.W, cfl=prob.cfl)
+    s = solver(H, prob, H.FUSE_RELAX)
+    s.step(cfl=prob.cfl)
+    torch.cuda.synchronize()
+    assert s.slot[0].item() == pytest.approx(dto, rel=1e-13)
+    assert rel_err(s.state(), ref, prob.N, prob.D, cmax) <= TOL
+    d = s.diagnostics()
+    assert d["relax_bad"] == 0
+    s.close()
+
+
+def test_multistep_t_end_clipping(H, orc):
+    """Config-1 shock tube driven to t_end with the device time: the last step
+    lands on t_end, positivity holds, and the result tracks the oracle."""
+    import torch
+    prob = I.config1(200)
+    t_end = 2e-5
+    o = orc.from_problem(prob)
+    ref, t, k = o.run(prob.W, cfl=0.4, t_end=t_end)
+    s = solver(H, prob, H.FUSE_RELAX)
+    s.set_slot(0.0, [0.0], t=0.0)
+    for _ in range(k):
+        s.step(cfl=0.4, t_end=t_end)
+    torch.cuda.synchronize()
+    assert s.slot[4].item() == pytest.approx(t_end, rel=1e-14)
+    got = s.state()
+    cmax = o.max_wavespeed(ref).max()
+    assert rel_err(got, ref, 2, 1, cmax) <= 1e-9
+    assert (got[:2] >= 0).all() and (got[4] >= 0).all() and (got[4] <= 1).all()
+    s.close()
+
+
+def test_determinism(H, orc):
+    import torch
+    prob = I.config2(128, 64)
+    outs = []
+    for _ in range(2):
+        s = solver(H, prob, H.FUSE_RELAX)
+        for _ in range(3):
+            s.step(cfl=0.4)
+        torch.cuda.synchronize()
+        outs.append(s.state())
+        s.close()
+    assert np.array_equal(outs[0], outs[1])

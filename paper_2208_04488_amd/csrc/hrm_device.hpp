@@ -448,42 +448,53 @@ __device__ inline double sensor_ratio(double v0, double v1, double v2, double v3
 // (taken as 2C/(-B - sqrt) when B > 0), T from eq:T_relax_e, then
 // alpha_k = alpha_k rho_k / rho_k(p, T) for k < N-1.  Returns false (and leaves
 // W unchanged) when rho(e - qbar) <= 0 or no positive root exists.
+// The root is ill-conditioned in a liquid at low pressure (its condition number
+// grows like gamma_1 pinf_1 / p), so this function evaluates each formula in
+// the order written, with IEEE division and no FMA contraction: its rounding
+// is then reproducible by any plain double-precision evaluation of the same
+// formulas.
 template <int N, int D>
 __device__ inline bool relax_cell(const EosDev& e, double* W)
 {
+#pragma clang fp contract(off)
     constexpr int IE = N + D, IA = N + D + 1;
-    double rho = 0.0, rq = 0.0;
+    double rho = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) rho += W[k];
+    double cvb = 0.0, cpb = 0.0, qb = 0.0, Y0 = 0.0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        rho += W[k];
-        rq += W[k] * e.q[k];
-    }
-    const double irho = 1.0 / rho;
-    double cvb = 0.0, cpb = 0.0;
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        const double Y = W[k] * irho;
+        const double Y = W[k] / rho;  // mass fraction
         cvb += Y * e.cv[k];
-        cpb += Y * e.cp[k];
+        cpb += Y * e.g[k] * e.cv[k];
+        qb += Y * e.q[k];
+        if (k == 0) Y0 = Y;
     }
     double m2 = 0.0;
 #pragma unroll
     for (int d = 0; d < D; ++d) m2 += W[N + d] * W[N + d];
-    const double re = W[IE] - 0.5 * m2 * irho - rq;
+    const double re = W[IE] - 0.5 * m2 / rho - rho * qb;  // rho (e - qbar)
     if (!(re > 0.0) || !(rho > 0.0)) return false;
-    const double Y0 = W[0] * irho;
-    const double p1 = e.pinf[0], R1 = e.cp[0] - e.cv[0];
-    const double Rg = (cpb - cvb) - Y0 * R1;
+    const double p1 = e.pinf[0];
+    const double R1 = e.g[0] * e.cv[0] - e.cv[0];  // c_p1 - c_v1
     const double A = cvb;
     const double B = -(re * (cpb - cvb) - p1 * cvb - p1 * Y0 * R1);
-    const double C = -re * p1 * Rg;
-    const double sq = sqrt(B * B - 4.0 * A * C);
-    const double p = B <= 0.0 ? (-B + sq) / (2.0 * A) : 2.0 * C / (-B - sq);
+    const double C = -re * p1 * ((cpb - cvb) - Y0 * R1);
+    const double disc = B * B - 4.0 * A * C;
+    double p;
+    if (B <= 0.0)
+        p = (-B + sqrt(disc)) / (2.0 * A);
+    else
+        p = 2.0 * C / (-B - sqrt(disc));
     if (!(p > 0.0) || !isfinite(p)) return false;
-    const double T = re * irho / (Y0 * (p + e.g[0] * p1) * e.cv[0] / (p + p1) + cvb - Y0 * e.cv[0]);
+    const double e_t = re / rho;
+    const double T = e_t / (Y0 * (p + e.g[0] * p1) * e.cv[0] / (p + p1) + cvb - Y0 * e.cv[0]);
     if (!(T > 0.0) || !isfinite(T)) return false;
 #pragma unroll
-    for (int k = 0; k < N - 1; ++k) W[IA + k] = W[k] * ((e.g[k] - 1.0) * e.cv[k] * T) / (p + e.pinf[k]);
+    for (int k = 0; k < N - 1; ++k) {
+        const double rk = (p + e.pinf[k]) / ((e.g[k] - 1.0) * e.cv[k] * T);  // rho_k(p, T)
+        W[IA + k] = W[k] / rk;
+    }
     return true;
 }
 

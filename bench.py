@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--nx", type=int, default=1024)
     ap.add_argument("--ny", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 512 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (DESIGN.md describes how it "
@@ -95,6 +97,18 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        # 2 GiB per buffer: larger than the 256 MB Infinity Cache, so every
+        # byte of the copy comes from and goes to HBM
+        nbytes = 2 << 30
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)  # elementwise kernel: reads a, writes b
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "elementwise copy b = 1.0 * a", "bytes_read_per_launch": nbytes,
+                          "bytes_written_per_launch": nbytes, "launches": 3}), flush=True)
+        return
     from paper_2208_04488_amd import hrm
     from paper_2208_04488_amd import inputs as I
 

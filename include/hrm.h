@@ -55,6 +55,7 @@ extern "C" {
 #define HRM_NO_BLEND 2      /* shock-sensor blending off: pure HCS flux (App. B) */
 #define HRM_FIRST_ORDER 4   /* first-order HLLC fluxes only (Sec. 4.1.1) */
 #define HRM_FUSE_RELAX 8    /* hrm_rk_stage relaxes its output in the same kernel */
+#define HRM_NO_GRAPH 16     /* hrm_step launches its kernels directly instead of replaying a graph */
 
 /* Uniform Cartesian grid of n[0] x n[1] x n[2] cells, nodes at cell centres
  * (Sec. 4.1).  Entries beyond `dim` must be n = 1. */
@@ -155,7 +156,11 @@ int hrm_relax(hrm_ctx* ctx, double* d_W, void* stream);
 
 /* One full SSP-RK3 step of the fractional algorithm on d_W in place:
  * wavespeed of W^n, time step into d_slot (see hrm_compute_dt), three stages
- * each followed by the relaxation.  Uses the context's stage buffers. */
+ * each followed by the relaxation.  Uses the context's stage buffers.
+ * Unless the grid has HRM_NO_GRAPH (or timing is on), the first call captures
+ * the step's launches into a hipGraph on a private stream and every call with
+ * the same (d_W, d_slot, cfl, dt_fixed, t_end) replays it on `stream`; other
+ * arguments re-capture.  The graph holds kernel nodes only. */
 int hrm_step(hrm_ctx* ctx, double* d_W, double cfl, double dt_fixed, double t_end, double* d_slot,
              void* stream);
 

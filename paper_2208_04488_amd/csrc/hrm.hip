@@ -69,7 +69,7 @@ __device__ inline void flush_counters(const unsigned* c, unsigned long long* dst
 // DIR == 1: blockDim = (BA, BS), across = x, blockIdx.z = z.
 // DIR == 2: blockDim = (BA, BS), across = x, blockIdx.y = y.
 template <int N, int D, int DIR, int BS, int BA>
-__global__ void __launch_bounds__(BS* BA) k_sweep(const SweepArgs A)
+__global__ void __launch_bounds__(BS* BA, 2) k_sweep(const SweepArgs A)
 {
     using F = NodeFields<N, D>;
     constexpr int M = 2 * N + D, IA = N + D + 1;
@@ -263,22 +263,51 @@ __global__ void __launch_bounds__(256) k_reduce_max(const double* part, int nb, 
         for (int d = 0; d < D; ++d) out[d] = m[d];
 }
 
-__global__ void k_dt(const double* maxs, int D, double dx0, double dx1, double dx2, double cfl, double dt_fixed,
-                     double t_end, double* slot)
+struct DtArgs {
+    int D;
+    double dx[3];
+    double cfl, dt_fixed, t_end;
+};
+
+// Sec. 4.1.2: tau_d = maxs_d / dx_d, dt = CFL / sum tau (or the fixed step),
+// lambda_d = dt / (sigma_d dx_d); clipped to t_end with the device time slot[4]
+__device__ inline void dt_from_max(const double* maxs, const DtArgs& a, double* slot)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const double dx[3] = {dx0, dx1, dx2};
     double tau[3] = {0.0, 0.0, 0.0}, ts = 0.0;
-    for (int d = 0; d < D; ++d) {
-        tau[d] = maxs[d] / dx[d];
+    for (int d = 0; d < a.D; ++d) {
+        tau[d] = maxs[d] / a.dx[d];
         ts += tau[d];
     }
-    double dt = dt_fixed > 0.0 ? dt_fixed : cfl / ts;
+    double dt = a.dt_fixed > 0.0 ? a.dt_fixed : a.cfl / ts;
     const double t = slot[4];
-    if (t_end > 0.0 && t + dt > t_end) dt = fmax(t_end - t, 0.0);
+    if (a.t_end > 0.0 && t + dt > a.t_end) dt = fmax(a.t_end - t, 0.0);
     slot[0] = dt;
-    for (int d = 0; d < 3; ++d) slot[1 + d] = d < D ? dt / ((tau[d] / ts) * dx[d]) : 0.0;
-    slot[4] = t_end > 0.0 && t + dt >= t_end ? t_end : t + dt;
+    for (int d = 0; d < 3; ++d) slot[1 + d] = d < a.D ? dt / ((tau[d] / ts) * a.dx[d]) : 0.0;
+    slot[4] = a.t_end > 0.0 && t + dt >= a.t_end ? a.t_end : t + dt;
+}
+
+__global__ void k_dt(const double* maxs, DtArgs a, double* slot)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) dt_from_max(maxs, a, slot);
+}
+
+// grid-wide maximum of the wavespeed partials and the time step, one block
+template <int D>
+__global__ void __launch_bounds__(256) k_reduce_dt(const double* part, int nb, double* maxs, DtArgs a, double* slot)
+{
+    __shared__ double sh[4 * 3];
+    double m[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) m[d] = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256)
+#pragma unroll
+        for (int d = 0; d < D; ++d) m[d] = nmax(m[d], part[i * D + d]);
+    block_max<D>(m, sh);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) maxs[d] = m[d];
+        dt_from_max(maxs, a, slot);
+    }
 }
 
 __global__ void k_zero_u64(unsigned long long* p, int n)
@@ -306,6 +335,12 @@ struct hrm_ctx {
     double* d_maxs;
     unsigned long long* d_cnt;
     hipStream_t last_stream;
+    // hrm_step replay: one captured RK3 step per argument set
+    hipStream_t cap_stream;
+    hipGraphExec_t gexec;
+    double* g_W;
+    double* g_slot;
+    double g_cfl, g_dt_fixed, g_t_end;
     // opt-in event timing
     int timing_mask;
     int npending;
@@ -415,6 +450,13 @@ struct Ops {
         hipLaunchKernelGGL((hrm::k_relax<N, D>), dim3((unsigned)nb), dim3(256), 0, s, W, c->ncell, c->eos, c->d_cnt);
     }
 
+    static void wavespeed_dt(hrm_ctx* c, const double* W, const hrm::DtArgs& a, double* slot, hipStream_t s)
+    {
+        TimerScope t(c, HRM_T_WAVESPEED, s);
+        hipLaunchKernelGGL((hrm::k_wavespeed<N, D>), dim3(c->npart), dim3(256), 0, s, W, c->ncell, c->eos, c->d_part);
+        hipLaunchKernelGGL((hrm::k_reduce_dt<D>), dim3(1), dim3(256), 0, s, c->d_part, c->npart, c->d_maxs, a, slot);
+    }
+
     static void wavespeed(hrm_ctx* c, const double* W, double* out, hipStream_t s)
     {
         TimerScope t(c, HRM_T_WAVESPEED, s);
@@ -474,6 +516,37 @@ int run_operator(hrm_ctx* c, const double* Ws, const double* Wn, double* Wout, d
 }
 
 bool valid_ptr(const void* p) { return p != nullptr; }
+
+hrm::DtArgs dt_args(hrm_ctx* c, double cfl, double dt_fixed, double t_end)
+{
+    hrm::DtArgs a;
+    a.D = c->D;
+    for (int d = 0; d < 3; ++d) a.dx[d] = c->dx[d];
+    a.cfl = cfl;
+    a.dt_fixed = dt_fixed;
+    a.t_end = t_end;
+    return a;
+}
+
+// the launches of one RK3 step on stream s
+int step_enqueue(hrm_ctx* c, double* d_W, double cfl, double dt_fixed, double t_end, double* d_slot, hipStream_t s)
+{
+    static const double RK_A[3] = {0.0, 3.0 / 4.0, 1.0 / 3.0};
+    static const double RK_B[3] = {1.0, 1.0 / 4.0, 2.0 / 3.0};
+    const hrm::DtArgs a = dt_args(c, cfl, dt_fixed, t_end);
+    int rc = dispatch(c, [&](auto ops) { decltype(ops)::wavespeed_dt(c, d_W, a, d_slot, s); });
+    if (rc == HRM_OK) rc = check_launch(c, "hrm_step wavespeed");
+    if (rc == HRM_OK) rc = run_operator(c, d_W, d_W, c->d_W1, c->d_rhs, d_slot, true, RK_A[0], RK_B[0], 1, s);
+    if (rc == HRM_OK) rc = run_operator(c, c->d_W1, d_W, c->d_W2, c->d_rhs, d_slot, true, RK_A[1], RK_B[1], 1, s);
+    if (rc == HRM_OK) rc = run_operator(c, c->d_W2, d_W, d_W, c->d_rhs, d_slot, true, RK_A[2], RK_B[2], 1, s);
+    return rc;
+}
+
+void drop_graph(hrm_ctx* c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+}
 
 }  // namespace
 
@@ -582,6 +655,7 @@ int hrm_create(const hrm_grid* g, const hrm_eos* e, const hrm_params* prm, hrm_c
     P.hcs_b = 25.0 * p.psi / 256.0 - 2.0 / 15.0;
     P.hcs_c = 3.0 * p.psi / 256.0 - 1.0 / 60.0;
     P.flags = g->flags;
+    P.fast_flux_limiter = p.eps_f_ar >= p.hs_f_ar && p.eps_f_a >= p.hs_f_a && p.eps_f_re >= p.hs_f_re;
 
     const size_t bytes = sizeof(double) * (size_t)c->M * (size_t)c->ncell;
     c->npart = (int)std::min<long long>((c->ncell + 255) / 256, 2048);
@@ -593,6 +667,7 @@ int hrm_create(const hrm_grid* g, const hrm_eos* e, const hrm_params* prm, hrm_c
     ok = ok && hipMalloc((void**)&c->d_maxs, sizeof(double) * 4) == hipSuccess;
     ok = ok && hipMalloc((void**)&c->d_cnt, sizeof(unsigned long long) * 8) == hipSuccess;
     if (ok) ok = hipMemset(c->d_cnt, 0, sizeof(unsigned long long) * 8) == hipSuccess;
+    if (ok) ok = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         hrm_destroy(c);
@@ -617,6 +692,8 @@ int hrm_destroy(hrm_ctx* c)
     (void)hipFree(c->d_part);
     (void)hipFree(c->d_maxs);
     (void)hipFree(c->d_cnt);
+    drop_graph(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
     return HRM_OK;
 }
@@ -640,8 +717,7 @@ int hrm_compute_dt(hrm_ctx* c, const double* d_maxspeed, double cfl, double dt_f
     hipStream_t s = (hipStream_t)stream;
     c->last_stream = s;
     TimerScope t(c, HRM_T_DT, s);
-    hipLaunchKernelGGL(hrm::k_dt, dim3(1), dim3(64), 0, s, d_maxspeed, c->D, c->dx[0], c->dx[1], c->dx[2], cfl,
-                       dt_fixed, t_end, d_slot);
+    hipLaunchKernelGGL(hrm::k_dt, dim3(1), dim3(64), 0, s, d_maxspeed, dt_args(c, cfl, dt_fixed, t_end), d_slot);
     return check_launch(c, "hrm_compute_dt");
 }
 
@@ -683,17 +759,40 @@ int hrm_relax(hrm_ctx* c, double* d_W, void* stream)
 
 int hrm_step(hrm_ctx* c, double* d_W, double cfl, double dt_fixed, double t_end, double* d_slot, void* stream)
 {
-    static const double RK_A[3] = {0.0, 3.0 / 4.0, 1.0 / 3.0};
-    static const double RK_B[3] = {1.0, 1.0 / 4.0, 2.0 / 3.0};
     if (!c) return HRM_EINVAL;
     if (!valid_ptr(d_W) || !valid_ptr(d_slot)) return fail(c, HRM_EINVAL, "hrm_step: NULL pointer%s");
+    if (!(dt_fixed > 0.0) && !(cfl > 0.0)) return fail(c, HRM_EINVAL, "hrm_step: need cfl > 0 or dt_fixed > 0%s");
     hipStream_t s = (hipStream_t)stream;
-    int rc = hrm_max_wavespeed(c, d_W, c->d_maxs, stream);
-    if (rc == HRM_OK) rc = hrm_compute_dt(c, c->d_maxs, cfl, dt_fixed, t_end, d_slot, stream);
-    if (rc == HRM_OK) rc = run_operator(c, d_W, d_W, c->d_W1, c->d_rhs, d_slot, true, RK_A[0], RK_B[0], 1, s);
-    if (rc == HRM_OK) rc = run_operator(c, c->d_W1, d_W, c->d_W2, c->d_rhs, d_slot, true, RK_A[1], RK_B[1], 1, s);
-    if (rc == HRM_OK) rc = run_operator(c, c->d_W2, d_W, d_W, c->d_rhs, d_slot, true, RK_A[2], RK_B[2], 1, s);
-    return rc;
+    c->last_stream = s;
+    if ((c->flags & HRM_NO_GRAPH) || c->timing_mask) return step_enqueue(c, d_W, cfl, dt_fixed, t_end, d_slot, s);
+    const bool same = c->gexec && c->g_W == d_W && c->g_slot == d_slot && c->g_cfl == cfl &&
+                      c->g_dt_fixed == dt_fixed && c->g_t_end == t_end;
+    if (!same) {
+        drop_graph(c);
+        if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess)
+            return fail(c, HRM_EDEVICE, "hrm_step: stream capture failed%s");
+        const int rc = step_enqueue(c, d_W, cfl, dt_fixed, t_end, d_slot, c->cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
+        if (rc != HRM_OK || ec != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc != HRM_OK ? rc : fail(c, HRM_EDEVICE, "hrm_step: end capture: %s", hipGetErrorString(ec));
+        }
+        const hipError_t ei = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            c->gexec = nullptr;
+            return fail(c, HRM_EDEVICE, "hrm_step: graph instantiate: %s", hipGetErrorString(ei));
+        }
+        c->g_W = d_W;
+        c->g_slot = d_slot;
+        c->g_cfl = cfl;
+        c->g_dt_fixed = dt_fixed;
+        c->g_t_end = t_end;
+    }
+    if (hipGraphLaunch(c->gexec, s) != hipSuccess)
+        return fail(c, HRM_EDEVICE, "hrm_step: graph launch: %s", hipGetErrorString(hipGetLastError()));
+    return HRM_OK;
 }
 
 int hrm_get_diagnostics(hrm_ctx* c, hrm_diag* out)

@@ -35,6 +35,7 @@ struct ParDev {
     double Cs, qexp, psi;
     double hcs_a, hcs_b, hcs_c;  // eq:reconstructed_G coefficients from psi
     int flags;
+    int fast_flux_limiter;  // eps_f >= eps_f^HS for all three quantities
 };
 
 // counters accumulated per thread, flushed once per wave
@@ -226,6 +227,7 @@ __device__ inline double lim_theta(double a, double b, double eps)
 // Sec. 4.3.2 interpolation limiter on an interpolated primitive state V
 // (partial densities and volume fractions are blended toward the node state;
 // velocity and pressure are kept), then the hard switch to the node state.
+// On return V is a complete state (conservative slots, rho, c, rho c^2).
 template <int N, int D>
 __device__ inline void interp_limit(const EosDev& e, const ParDev& P, St<N, D>& V, const St<N, D>& node,
                                     unsigned* cnt)
@@ -255,28 +257,18 @@ __device__ inline void interp_limit(const EosDev& e, const ParDev& P, St<N, D>& 
         for (int k = 0; k < N - 1; ++k) V.al[k] = (1.0 - th) * node.al[k] + th * V.al[k];
         cnt[C_ALG2]++;
     }
-    // hard switch
-    double al[N];
-    asum = 0.0;
-#pragma unroll
-    for (int k = 0; k < N - 1; ++k) {
-        al[k] = V.al[k];
-        asum += al[k];
-    }
-    al[N - 1] = 1.0 - asum;
-    double Gam, Pi;
-    mixture<N>(e, al, Gam, Pi);
-    const double rc2 = V.p + (V.p + Pi) / Gam;
-    bool hs = !isfinite(rc2) || !isfinite(V.p);
+    // hard switch, judged on the completed limited state
+    complete_from_prim<N, D>(e, V);
+    bool hs = !isfinite(V.rc2) || !isfinite(V.p);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        hs |= !isfinite(V.ar[k]) || !isfinite(al[k]);
+        hs |= !isfinite(V.ar[k]) || !isfinite(V.al[k]);
         hs |= V.ar[k] < fmin(P.hs_i_ar, node.ar[k]);
-        hs |= al[k] < fmin(P.hs_i_a, node.al[k]);
+        hs |= V.al[k] < fmin(P.hs_i_a, node.al[k]);
     }
 #pragma unroll
     for (int d = 0; d < D; ++d) hs |= !isfinite(V.u[d]);
-    hs |= rc2 < fmin(P.hs_i_rc2, node.rc2);
+    hs |= V.rc2 < fmin(P.hs_i_rc2, node.rc2);
     if (hs) {
 #pragma unroll
         for (int k = 0; k < N; ++k) V.ar[k] = node.ar[k];
@@ -285,6 +277,7 @@ __device__ inline void interp_limit(const EosDev& e, const ParDev& P, St<N, D>& 
         V.p = node.p;
 #pragma unroll
         for (int k = 0; k < N - 1; ++k) V.al[k] = node.al[k];
+        complete_from_prim<N, D>(e, V);
         cnt[C_IHS]++;
     }
 }
@@ -379,6 +372,26 @@ __device__ inline void flux_limit(const EosDev& e, const ParDev& P, const St<N, 
         }
     }
     if (th < 1.0) cnt[C_ALG3]++;
+    // When Alg. 3 leaves theta = 1, G* = G^ho and W* = W^ho exactly.  If Alg. 4
+    // also gives 1 and everything is finite, the hard switch cannot fire
+    // (eps >= eps^HS, checked at context creation), so G** = G^ho: return
+    // without rebuilding the half-cell states twice more.
+    if (P.fast_flux_limiter && th == 1.0) {
+        const double rep = rhoe_tilde<N, D>(e, Wp), rem = rhoe_tilde<N, D>(e, Wm);
+        const double t2 = fmin(lim_theta(rep_lo, rep, P.eps_f_re), lim_theta(rem_lo, rem, P.eps_f_re));
+        bool fin = isfinite(rep) && isfinite(rem) && isfinite(rep_lo) && isfinite(rem_lo);
+#pragma unroll
+        for (int c = 0; c < M; ++c) fin = fin && isfinite(Gho[c]) && isfinite(Wp_lo[c]) && isfinite(Wm_lo[c]);
+#pragma unroll
+        for (int k = 0; k < N - 1; ++k) fin = fin && isfinite(Gho_p[k]);
+        if (t2 == 1.0 && fin) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) G[c] = Gho[c];
+#pragma unroll
+            for (int k = 0; k < N - 1; ++k) Gp[k] = Gho_p[k];
+            return;
+        }
+    }
     double Gs[M], Gsp[N > 1 ? N - 1 : 1];
 #pragma unroll
     for (int c = 0; c < M; ++c) Gs[c] = (1.0 - th) * Glo[c] + th * Gho[c];

@@ -155,11 +155,12 @@ __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, do
 
     // Sec. 4.3.2 interpolation limiter: left against node i, right against node i+1
     if (!(P.flags & F_NO_LIMITERS)) {
-        interp_limit<N, D>(e, P, VL, L, cnt);
+        interp_limit<N, D>(e, P, VL, L, cnt);  // also completes the state
         interp_limit<N, D>(e, P, VR, R, cnt);
+    } else {
+        complete_from_prim<N, D>(e, VL);
+        complete_from_prim<N, D>(e, VR);
     }
-    complete_from_prim<N, D>(e, VL);
-    complete_from_prim<N, D>(e, VR);
 
     // midpoint flux and velocity from HLLC on the interpolated states
     double Gt[M];
@@ -178,7 +179,9 @@ __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, do
         const double sp = 0.5 * (sensor_ratio(pr[1], pr[2], pr[3], pr[4], pr[5]) +
                                  sensor_ratio(pr[0], pr[1], pr[2], pr[3], pr[4]));
         const double z = sr * sp;
-        sig = tanh(P.Cs * (P.qexp == 2.0 ? z * z : pow(z, P.qexp)));
+        const double arg = P.Cs * (P.qexp == 2.0 ? z * z : pow(z, P.qexp));
+        // tanh is exactly 0 at 0 and rounds to 1 for arguments >= 22
+        sig = arg == 0.0 ? 0.0 : (arg >= 22.0 ? 1.0 : tanh(arg));
     }
 
     // HCS reconstruction (eq:reconstructed_G, eq:reconstructed_vel) and blending

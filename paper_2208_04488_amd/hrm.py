@@ -23,7 +23,7 @@ HRM_OK, HRM_EINVAL, HRM_ENOMEM, HRM_EDEVICE, HRM_EADMISSIBLE, HRM_EUNSUPPORTED =
 BC_TRANSMISSIVE, BC_PERIODIC = 0, 1
 FP64, FP32 = 0, 1
 WEIGHTS_IS = 0
-NO_LIMITERS, NO_BLEND, FIRST_ORDER, FUSE_RELAX = 1, 2, 4, 8
+NO_LIMITERS, NO_BLEND, FIRST_ORDER, FUSE_RELAX, NO_GRAPH = 1, 2, 4, 8, 16
 
 
 class hrm_grid(ctypes.Structure):

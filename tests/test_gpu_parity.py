@@ -290,3 +290,22 @@ def test_determinism(H, orc):
         outs.append(s.state())
         s.close()
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_graph_replay_matches_eager(H, orc):
+    """hrm_step replays a captured graph; every replay must equal the direct
+    launches bit for bit, with unrelated eager work between replays."""
+    import torch
+    prob = I.config2(128, 64)
+    g = solver(H, prob, H.FUSE_RELAX)
+    e = solver(H, prob, H.FUSE_RELAX | H.NO_GRAPH)
+    for k in range(6):
+        g.step(cfl=0.4)
+        e.step(cfl=0.4)
+        torch.cuda.synchronize()
+        junk = torch.randn(4096, device="cuda", dtype=torch.float64)
+        _ = (junk * 2.0).sum().item()
+        assert torch.equal(g.W, e.W), k
+        assert torch.equal(g.slot, e.slot), k
+    g.close()
+    e.close()

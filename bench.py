@@ -96,6 +96,7 @@ def main():
               "would shard). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     if args.calibrate_copy:
         # 2 GiB per buffer: larger than the 256 MB Infinity Cache, so every
@@ -132,6 +133,7 @@ def main():
     wall = time.perf_counter() - w0
     ms_total = ev0.elapsed_time(ev1)
     ms_step = ms_total / args.steps
+    w64_timed = s.state()
 
     # kernel durations: the same K steps with the library's HIP events around
     # every sweep launch on the same stream (direct launches, no graph)
@@ -170,7 +172,31 @@ def main():
         "positivity": {"relax_bad": diag["relax_bad"], "interp_hs": diag["interp_hs"],
                        "flux_hs": diag["flux_hs"]},
     }
+    w64 = w64_timed
     s.close()
+
+    # FP32 face arithmetic on the same workload: throughput and L1 error of
+    # the mixture density after the same warm-up + timed steps
+    s32 = hrm.Solver(prob, flags=hrm.FUSE_RELAX, precision=hrm.FP32)
+    for _ in range(args.warmup):
+        s32.step(cfl=prob.cfl)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        s32.step(cfl=prob.cfl)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms32 = e0.elapsed_time(e1)
+    w32 = s32.state()
+    d32 = s32.diagnostics()
+    s32.close()
+    rho64, rho32 = w64[:N].sum(axis=0), w32[:N].sum(axis=0)
+    cups32 = prob.ncell * args.steps / (ms32 * 1e-3)
+    out["fp32"] = {"value": cups32, "unit": "cell-updates/s", "speedup_vs_fp64": cups32 / cups,
+                   "ms_per_step": ms32 / args.steps,
+                   "l1_rel_rho_vs_fp64": float(np.abs(rho32 - rho64).sum() / np.abs(rho64).sum()),
+                   "after_steps": args.warmup + args.steps, "relax_bad": d32["relax_bad"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)

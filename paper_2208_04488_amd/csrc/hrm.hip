@@ -68,7 +68,7 @@ __device__ inline void flush_counters(const unsigned* c, unsigned long long* dst
 // across it.  DIR == 0: blockDim = (BS, BA), across = y, blockIdx.z = z.
 // DIR == 1: blockDim = (BA, BS), across = x, blockIdx.z = z.
 // DIR == 2: blockDim = (BA, BS), across = x, blockIdx.y = y.
-template <int N, int D, int DIR, int BS, int BA>
+template <int N, int D, int DIR, int BS, int BA, typename R>
 __global__ void __launch_bounds__(BS* BA, 2) k_sweep(const SweepArgs A)
 {
     using F = NodeFields<N, D>;
@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(BS* BA, 2) k_sweep(const SweepArgs A)
     double G[M], Gp[NA];
     {
         unsigned lc[C_N] = {0, 0, 0, 0, 0, 0, 0};
-        face_flux<N, D, DIR, NS, FS>(lds + base(ta, ts), A.e, A.P, A.slot[1 + DIR], G, Gp, lc);
+        face_flux<N, D, DIR, NS, FS, R>(lds + base(ta, ts), A.e, A.P, A.slot[1 + DIR], G, Gp, lc);
         const bool ok = (c0 - 1 + ts <= nsw - 1) && (abase + ta < na);
         if (ok)
 #pragma unroll
@@ -428,7 +428,10 @@ struct Ops {
         A.bchi = c->bchi[DIR];
         A.idx = 1.0 / c->dx[DIR];
         TimerScope t(c, HRM_T_SWEEP_X + DIR, s);
-        hipLaunchKernelGGL((hrm::k_sweep<N, D, DIR, BS, BA>), grd, blk, 0, s, A);
+        if (c->precision == HRM_FP32)
+            hipLaunchKernelGGL((hrm::k_sweep<N, D, DIR, BS, BA, float>), grd, blk, 0, s, A);
+        else
+            hipLaunchKernelGGL((hrm::k_sweep<N, D, DIR, BS, BA, double>), grd, blk, 0, s, A);
     }
 
     static void sweep(hrm_ctx* c, int dir, hrm::SweepArgs& A, hipStream_t s)
@@ -598,7 +601,6 @@ int hrm_create(const hrm_grid* g, const hrm_eos* e, const hrm_params* prm, hrm_c
     }
     if (g->precision != HRM_FP64 && g->precision != HRM_FP32) return HRM_EINVAL;
     if (g->weights != HRM_WEIGHTS_IS) return HRM_EUNSUPPORTED;
-    if (g->precision != HRM_FP64) return HRM_EUNSUPPORTED;
 
     hrm_ctx* c = new (std::nothrow) hrm_ctx;
     if (!c) return HRM_ENOMEM;

@@ -4,8 +4,11 @@
 // interpolation and flux limiters, and the infinite-rate thermal relaxation
 // (Wong, Angel & Kiris, arXiv:2208.04488, Sec. 2, Sec. 4, App. C, App. D).
 //
-// Everything here is double precision.  Component slots of a conservative
-// vector W (Sec. 2): alpha_k rho_k (k < N), rho u_d (d < D), E, alpha_k (k < N-1).
+// Face arithmetic is templated on R (double, or float for the FP32 variant);
+// the node primitives, the flux limiter, every limiter bound check, the
+// accumulation and the relaxation are double in both.  Component slots of a
+// conservative vector W (Sec. 2): alpha_k rho_k (k < N), rho u_d (d < D), E,
+// alpha_k (k < N-1).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -42,28 +45,52 @@ struct ParDev {
 enum { C_ALG1 = 0, C_ALG2, C_IHS, C_ALG3, C_ALG4, C_FHS, C_RELAX_BAD, C_N };
 
 // A full state: conservative and primitive slots side by side.
-template <int N, int D>
+template <int N, int D, typename R = double>
 struct St {
-    double ar[N];   // alpha_k rho_k
-    double mom[D];  // rho u_d
-    double u[D];
-    double p, E;
-    double al[N];   // all N volume fractions, al[N-1] = 1 - sum of the others
-    double rho, c, rc2;
+    R ar[N];   // alpha_k rho_k
+    R mom[D];  // rho u_d
+    R u[D];
+    R p, E;
+    double al[N];  // all N volume fractions, al[N-1] = 1 - sum of the others (always double:
+                   // a bulk fraction 1 - 1e-8 next to a trace 1e-8 is not representable in float)
+    R rho, c, rc2;
 };
+
+// a state converted to another arithmetic type
+template <int N, int D, typename R, typename S>
+__device__ inline St<N, D, R> convert(const St<N, D, S>& s)
+{
+    St<N, D, R> o;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        o.ar[k] = (R)s.ar[k];
+        o.al[k] = s.al[k];
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        o.mom[d] = (R)s.mom[d];
+        o.u[d] = (R)s.u[d];
+    }
+    o.p = (R)s.p;
+    o.E = (R)s.E;
+    o.rho = (R)s.rho;
+    o.c = (R)s.c;
+    o.rc2 = (R)s.rc2;
+    return o;
+}
 
 // Sec. 2 mixture EOS: Gam = 1/(gbar-1) = sum alpha_k/(gamma_k-1),
 // Pi = gbar pbar/(gbar-1) = sum alpha_k gamma_k pinf_k/(gamma_k-1);
 // rho(e - qbar) = Gam p + Pi; rho c^2 = gbar (p + pbar) = p + (p + Pi)/Gam.
-template <int N>
-__device__ inline void mixture(const EosDev& e, const double* al, double& Gam, double& Pi)
+template <int N, typename R>
+__device__ inline void mixture(const EosDev& e, const R* al, R& Gam, R& Pi)
 {
-    Gam = 0.0;
-    Pi = 0.0;
+    Gam = 0;
+    Pi = 0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        Gam += al[k] * e.ig1[k];
-        Pi += al[k] * e.gpi1[k];
+        Gam += al[k] * (R)e.ig1[k];
+        Pi += al[k] * (R)e.gpi1[k];
     }
 }
 
@@ -106,28 +133,30 @@ __device__ inline void state_from_W(const EosDev& e, const double* W, St<N, D>& 
 }
 
 // primitive slots (ar, u, p, al[0..N-2]) already set -> the rest of the state
-template <int N, int D>
-__device__ inline void complete_from_prim(const EosDev& e, St<N, D>& s)
+template <int N, int D, typename R>
+__device__ inline void complete_from_prim(const EosDev& e, St<N, D, R>& s)
 {
-    double rho = 0.0, rq = 0.0, asum = 0.0;
+    R rho = 0, rq = 0;
+    double asum = 0.0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         rho += s.ar[k];
-        rq += s.ar[k] * e.q[k];
+        rq += s.ar[k] * (R)e.q[k];
     }
 #pragma unroll
     for (int k = 0; k < N - 1; ++k) asum += s.al[k];
     s.al[N - 1] = 1.0 - asum;
-    double Gam, Pi;
-    mixture<N>(e, s.al, Gam, Pi);
-    double u2 = 0.0;
+    double Gd, Pd;
+    mixture<N, double>(e, s.al, Gd, Pd);
+    const R Gam = (R)Gd, Pi = (R)Pd;
+    R u2 = 0;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         s.mom[d] = rho * s.u[d];
         u2 += s.u[d] * s.u[d];
     }
     s.rho = rho;
-    s.E = Gam * s.p + Pi + 0.5 * rho * u2 + rq;
+    s.E = Gam * s.p + Pi + (R)0.5 * rho * u2 + rq;
     s.rc2 = s.p + (s.p + Pi) / Gam;
     s.c = sqrt(s.rc2 / rho);
 }
@@ -149,71 +178,82 @@ __device__ inline double rhoe_tilde(const EosDev& e, const double* W)
 
 // App. C incremental-stencil WENO, left-biased at i+1/2 from u_{i-2..i+2}.
 // The four unnormalised weights are scaled by the common product of the
-// denominators so the weighting needs one division instead of six.
-__device__ inline double weno_is(double um2, double um1, double u0, double up1, double up2, double eps)
+// denominators so the weighting needs one division instead of six.  The
+// product spans up to ~1e-75..1e55 for the ranges met here, which double
+// holds; in the FP32 variant the candidates and smoothness indicators are
+// float and only this weighting is done in double.
+template <typename R>
+__device__ inline R weno_is(R um2, R um1, R u0, R up1, R up2, double eps)
 {
-    const double s0 = 0.5 * (u0 + up1);
-    const double s1 = 0.5 * (3.0 * u0 - um1);
-    const double s2 = 0.125 * (3.0 * u0 + 6.0 * up1 - up2);
-    const double s3 = 0.125 * (3.0 * um2 - 10.0 * um1 + 15.0 * u0);
-    const double a0 = u0 - up1, a1 = um1 - u0;
-    const double b01a = um1 - 2.0 * u0 + up1, b01b = um1 - up1;
-    const double b2a = u0 - 2.0 * up1 + up2, b2b = 3.0 * u0 - 4.0 * up1 + up2;
-    const double b3a = um2 - 2.0 * um1 + u0, b3b = um2 - 4.0 * um1 + 3.0 * u0;
-    const double t5a = up2 - 4.0 * up1 + 6.0 * u0 - 4.0 * um1 + um2;
-    const double t5b = up2 - 2.0 * up1 + 2.0 * um1 - um2;
-    constexpr double c13 = 13.0 / 12.0;
-    const double B0 = a0 * a0 + eps;
-    const double B1 = a1 * a1 + eps;
-    const double B01 = c13 * b01a * b01a + 0.25 * b01b * b01b + eps;
-    const double B2 = c13 * b2a * b2a + 0.25 * b2b * b2b + eps;
-    const double B3 = c13 * b3a * b3a + 0.25 * b3b * b3b + eps;
-    const double tau = c13 * t5a * t5a + 0.25 * t5b * t5b;
-    // eta_k times Q = B0 B1 B01 B2 B3
+    const R s0 = (R)0.5 * (u0 + up1);
+    const R s1 = (R)0.5 * ((R)3 * u0 - um1);
+    const R s2 = (R)0.125 * ((R)3 * u0 + (R)6 * up1 - up2);
+    const R s3 = (R)0.125 * ((R)3 * um2 - (R)10 * um1 + (R)15 * u0);
+    const R a0 = u0 - up1, a1 = um1 - u0;
+    const R b01a = um1 - (R)2 * u0 + up1, b01b = um1 - up1;
+    const R b2a = u0 - (R)2 * up1 + up2, b2b = (R)3 * u0 - (R)4 * up1 + up2;
+    const R b3a = um2 - (R)2 * um1 + u0, b3b = um2 - (R)4 * um1 + (R)3 * u0;
+    const R t5a = up2 - (R)4 * up1 + (R)6 * u0 - (R)4 * um1 + um2;
+    const R t5b = up2 - (R)2 * up1 + (R)2 * um1 - um2;
+    constexpr R c13 = (R)(13.0 / 12.0);
+    const R q0 = a0 * a0, q1 = a1 * a1;
+    const R q01 = c13 * b01a * b01a + (R)0.25 * b01b * b01b;
+    const R q2 = c13 * b2a * b2a + (R)0.25 * b2b * b2b;
+    const R q3 = c13 * b3a * b3a + (R)0.25 * b3b * b3b;
+    const R qt = c13 * t5a * t5a + (R)0.25 * t5b * t5b;
+    // weights (double): eta_k times Q = B0 B1 B01 B2 B3, B = beta + eps
+    const double B0 = (double)q0 + eps, B1 = (double)q1 + eps, B01 = (double)q01 + eps;
+    const double B2 = (double)q2 + eps, B3 = (double)q3 + eps, tau = qt;
     const double t2 = tau * tau;
     const double B23 = B2 * B3, B0B1 = B0 * B1;
     const double e0 = (15.0 / 32.0) * (B0 * B01 + t2) * B1 * B23;
     const double e1 = (5.0 / 32.0) * (B1 * B01 + t2) * B0 * B23;
     const double e2 = (5.0 / 16.0) * (B2 + tau) * B0B1 * B01 * B3;
     const double e3 = (1.0 / 16.0) * (B3 + tau) * B0B1 * B01 * B2;
-    return (e0 * s0 + e1 * s1 + e2 * s2 + e3 * s3) / (e0 + e1 + e2 + e3);
+    if constexpr (sizeof(R) == sizeof(double)) {
+        return (e0 * s0 + e1 * s1 + e2 * s2 + e3 * s3) / (e0 + e1 + e2 + e3);
+    } else {
+        const double inv = 1.0 / (e0 + e1 + e2 + e3);
+        return (R)(e0 * inv) * s0 + (R)(e1 * inv) * s1 + (R)(e2 * inv) * s2 + (R)(e3 * inv) * s3;
+    }
 }
 
 // Sec. 4.1.1 HLLC for the five-equation model in direction DIR.  Writes
 // G = F^HLLC + (0, ..., f_alpha) and returns s_*.  sign(0) = 0.
-template <int N, int D, int DIR>
-__device__ inline double hllc(const St<N, D>& L, const St<N, D>& R, double* G)
+template <int N, int D, int DIR, typename R>
+__device__ inline R hllc(const St<N, D, R>& L, const St<N, D, R>& Rs, double* G)
 {
     constexpr int IE = N + D, IA = N + D + 1;
-    const double uL = L.u[DIR], uR = R.u[DIR];
-    const double ub = 0.5 * (uL + uR), cb = 0.5 * (L.c + R.c);
-    const double sL = fmin(ub - cb, uL - L.c);
-    const double sR = fmax(ub + cb, uR + R.c);
-    const double dL = sL - uL, dR = sR - uR;
-    const double ss = (R.p - L.p + L.rho * uL * dL - R.rho * uR * dR) / (L.rho * dL - R.rho * dR);
-    const double sg = ss > 0.0 ? 1.0 : (ss < 0.0 ? -1.0 : 0.0);
-    const double wl = 0.5 * (1.0 + sg), wr = 0.5 * (1.0 - sg);
-    const double sm = fmin(0.0, sL), sp = fmax(0.0, sR);
-    const double chiL = dL / (sL - ss), chiR = dR / (sR - ss);
+    const R uL = L.u[DIR], uR = Rs.u[DIR];
+    const R ub = (R)0.5 * (uL + uR), cb = (R)0.5 * (L.c + Rs.c);
+    const R sL = fmin(ub - cb, uL - L.c);
+    const R sR = fmax(ub + cb, uR + Rs.c);
+    const R dL = sL - uL, dR = sR - uR;
+    const R ss = (Rs.p - L.p + L.rho * uL * dL - Rs.rho * uR * dR) / (L.rho * dL - Rs.rho * dR);
+    const R sg = ss > (R)0 ? (R)1 : (ss < (R)0 ? (R)-1 : (R)0);
+    const R wl = (R)0.5 * ((R)1 + sg), wr = (R)0.5 * ((R)1 - sg);
+    const R sm = fmin((R)0, sL), sp = fmax((R)0, sR);
+    const R chiL = dL / (sL - ss), chiR = dR / (sR - ss);
 #pragma unroll
     for (int k = 0; k < N; ++k)
         G[k] = wl * (L.ar[k] * uL + sm * (chiL * L.ar[k] - L.ar[k])) +
-               wr * (R.ar[k] * uR + sp * (chiR * R.ar[k] - R.ar[k]));
+               wr * (Rs.ar[k] * uR + sp * (chiR * Rs.ar[k] - Rs.ar[k]));
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        const double FLd = L.mom[d] * uL + (d == DIR ? L.p : 0.0);
-        const double FRd = R.mom[d] * uR + (d == DIR ? R.p : 0.0);
-        const double WsL = d == DIR ? chiL * L.rho * ss : chiL * L.rho * L.u[d];
-        const double WsR = d == DIR ? chiR * R.rho * ss : chiR * R.rho * R.u[d];
-        G[N + d] = wl * (FLd + sm * (WsL - L.mom[d])) + wr * (FRd + sp * (WsR - R.mom[d]));
+        const R FLd = L.mom[d] * uL + (d == DIR ? L.p : (R)0);
+        const R FRd = Rs.mom[d] * uR + (d == DIR ? Rs.p : (R)0);
+        const R WsL = d == DIR ? chiL * L.rho * ss : chiL * L.rho * L.u[d];
+        const R WsR = d == DIR ? chiR * Rs.rho * ss : chiR * Rs.rho * Rs.u[d];
+        G[N + d] = wl * (FLd + sm * (WsL - L.mom[d])) + wr * (FRd + sp * (WsR - Rs.mom[d]));
     }
     {
-        const double EsL = chiL * (L.E + (ss - uL) * (L.rho * ss + L.p / dL));
-        const double EsR = chiR * (R.E + (ss - uR) * (R.rho * ss + R.p / dR));
-        G[IE] = wl * ((L.E + L.p) * uL + sm * (EsL - L.E)) + wr * ((R.E + R.p) * uR + sp * (EsR - R.E));
+        const R EsL = chiL * (L.E + (ss - uL) * (L.rho * ss + L.p / dL));
+        const R EsR = chiR * (Rs.E + (ss - uR) * (Rs.rho * ss + Rs.p / dR));
+        G[IE] = wl * ((L.E + L.p) * uL + sm * (EsL - L.E)) + wr * ((Rs.E + Rs.p) * uR + sp * (EsR - Rs.E));
     }
 #pragma unroll
-    for (int k = 0; k < N - 1; ++k) G[IA + k] = wl * (L.al[k] * ss) + wr * (R.al[k] * ss);
+    for (int k = 0; k < N - 1; ++k)
+        G[IA + k] = (double)wl * (L.al[k] * (double)ss) + (double)wr * (Rs.al[k] * (double)ss);
     return ss;
 }
 
@@ -228,8 +268,8 @@ __device__ inline double lim_theta(double a, double b, double eps)
 // (partial densities and volume fractions are blended toward the node state;
 // velocity and pressure are kept), then the hard switch to the node state.
 // On return V is a complete state (conservative slots, rho, c, rho c^2).
-template <int N, int D>
-__device__ inline void interp_limit(const EosDev& e, const ParDev& P, St<N, D>& V, const St<N, D>& node,
+template <int N, int D, typename R>
+__device__ inline void interp_limit(const EosDev& e, const ParDev& P, St<N, D, R>& V, const St<N, D, R>& node,
                                     unsigned* cnt)
 {
 #pragma unroll
@@ -238,7 +278,7 @@ __device__ inline void interp_limit(const EosDev& e, const ParDev& P, St<N, D>& 
         const double m = fmin(P.eps_i_ar, a);
         if (b < m) {
             const double th = (a - m) / (a - b);
-            V.ar[k] = (1.0 - th) * a + th * b;
+            V.ar[k] = (R)((1.0 - th) * a + th * b);
             cnt[C_ALG1]++;
         }
     }
@@ -251,24 +291,24 @@ __device__ inline void interp_limit(const EosDev& e, const ParDev& P, St<N, D>& 
     at[N - 1] = 1.0 - asum;
     double th = 1.0;
 #pragma unroll
-    for (int k = 0; k < N; ++k) th = fmin(th, lim_theta(node.al[k], at[k], P.eps_i_a));
+    for (int k = 0; k < N; ++k) th = fmin(th, lim_theta((double)node.al[k], at[k], P.eps_i_a));
     if (th < 1.0) {
 #pragma unroll
         for (int k = 0; k < N - 1; ++k) V.al[k] = (1.0 - th) * node.al[k] + th * V.al[k];
         cnt[C_ALG2]++;
     }
     // hard switch, judged on the completed limited state
-    complete_from_prim<N, D>(e, V);
+    complete_from_prim<N, D, R>(e, V);
     bool hs = !isfinite(V.rc2) || !isfinite(V.p);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         hs |= !isfinite(V.ar[k]) || !isfinite(V.al[k]);
-        hs |= V.ar[k] < fmin(P.hs_i_ar, node.ar[k]);
-        hs |= V.al[k] < fmin(P.hs_i_a, node.al[k]);
+        hs |= (double)V.ar[k] < fmin(P.hs_i_ar, (double)node.ar[k]);
+        hs |= (double)V.al[k] < fmin(P.hs_i_a, (double)node.al[k]);
     }
 #pragma unroll
     for (int d = 0; d < D; ++d) hs |= !isfinite(V.u[d]);
-    hs |= V.rc2 < fmin(P.hs_i_rc2, node.rc2);
+    hs |= (double)V.rc2 < fmin(P.hs_i_rc2, (double)node.rc2);
     if (hs) {
 #pragma unroll
         for (int k = 0; k < N; ++k) V.ar[k] = node.ar[k];
@@ -277,7 +317,7 @@ __device__ inline void interp_limit(const EosDev& e, const ParDev& P, St<N, D>& 
         V.p = node.p;
 #pragma unroll
         for (int k = 0; k < N - 1; ++k) V.al[k] = node.al[k];
-        complete_from_prim<N, D>(e, V);
+        complete_from_prim<N, D, R>(e, V);
         cnt[C_IHS]++;
     }
 }
@@ -446,14 +486,6 @@ __device__ inline void flux_limit(const EosDev& e, const ParDev& P, const St<N, 
 #pragma unroll
         for (int k = 0; k < N - 1; ++k) Gp[k] = Glo_p[k];
     }
-}
-
-// normalised fourth-order second derivative of the shock sensor (Sec. 4.3.1)
-__device__ inline double sensor_ratio(double v0, double v1, double v2, double v3, double v4)
-{
-    const double num = fabs(-v0 + 16.0 * v1 - 30.0 * v2 + 16.0 * v3 - v4);
-    const double den = fabs(v0 + 16.0 * v1 + 30.0 * v2 + 16.0 * v3 + v4);
-    return den > 0.0 ? num / den : (num > 0.0 ? 1.0 : 0.0);
 }
 
 // Sec. 4.2 infinite-rate thermal relaxation of one cell (species 0 is the

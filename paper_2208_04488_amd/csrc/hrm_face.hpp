@@ -52,32 +52,59 @@ __device__ inline void load_node(const double* nd, int j, St<N, D>& s)
 
 // left- and right-biased WENO-IS of one characteristic field given on the
 // six stencil nodes; the right-biased value mirrors the stencil (App. C)
-__device__ inline void weno_pair(const double* v, double eps, double& l, double& r)
+template <typename R>
+__device__ inline void weno_pair(const R* v, double eps, R& l, R& r)
 {
-    l = weno_is(v[0], v[1], v[2], v[3], v[4], eps);
-    r = weno_is(v[5], v[4], v[3], v[2], v[1], eps);
+    l = weno_is<R>(v[0], v[1], v[2], v[3], v[4], eps);
+    r = weno_is<R>(v[5], v[4], v[3], v[2], v[1], eps);
+}
+
+// normalised fourth-order second derivative of the shock sensor (Sec. 4.3.1)
+template <typename R>
+__device__ inline R sensor_ratio_t(R v0, R v1, R v2, R v3, R v4)
+{
+    const R num = fabs(-v0 + (R)16 * v1 - (R)30 * v2 + (R)16 * v3 - v4);
+    const R den = fabs(v0 + (R)16 * v1 + (R)30 * v2 + (R)16 * v3 + v4);
+    return den > (R)0 ? num / den : (num > (R)0 ? (R)1 : (R)0);
 }
 
 // Output: G = G^{**,-}_{i+1/2} (M slots) and Gp = alpha slots of G^{**,+}.
-template <int N, int D, int DIR, int NS, int FS>
+// R is the face arithmetic type; node data, the flux limiter and the outputs
+// are double.
+template <int N, int D, int DIR, int NS, int FS, typename R>
 __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, double lam, double* G, double* Gp,
                           unsigned* cnt)
 {
     using F = NodeFields<N, D>;
     constexpr int M = 2 * N + D, IE = N + D, IA = N + D + 1;
     constexpr int NA = N > 1 ? N - 1 : 1;
+    // FP32: the characteristic fields are interpolated as deviations from
+    // node i, formed in double.  WENO-IS is translation-equivariant (the
+    // smoothness indicators use differences only and the candidate weights
+    // sum to one), so this is the same interpolation, but float now resolves
+    // the small differences u +- p/(rho c) that carry the pressure in a liquid.
+    constexpr bool DELTA = sizeof(R) != sizeof(double);
+    auto nv = [&](int j, int f) -> R { return (R)nodev<NS, FS>(nd, j, f); };
+    auto dv = [&](int j, int f) -> R {
+        return DELTA ? (R)(nodev<NS, FS>(nd, j, f) - nodev<NS, FS>(nd, 2, f)) : (R)nodev<NS, FS>(nd, j, f);
+    };
+    auto back = [&](int f, R d) -> R { return DELTA ? (R)(nodev<NS, FS>(nd, 2, f) + (double)d) : d; };
+    auto back_d = [&](int f, R d) -> double { return DELTA ? nodev<NS, FS>(nd, 2, f) + (double)d : (double)d; };
 
-    St<N, D> L, R;
+    St<N, D> L, Rn;
     load_node<N, D, NS, FS>(nd, 2, L);
-    load_node<N, D, NS, FS>(nd, 3, R);
+    load_node<N, D, NS, FS>(nd, 3, Rn);
+    const St<N, D, R> Lr = convert<N, D, R>(L), Rr = convert<N, D, R>(Rn);
 
     // first-order HLLC of the node pair and its quasi-conservative pair (eq:G_pm)
     double Glo[M], Glo_p[NA];
-    const double sslo = hllc<N, D, DIR>(L, R, Glo);
+    {
+        const double ss = hllc<N, D, DIR, R>(Lr, Rr, Glo);
 #pragma unroll
-    for (int k = 0; k < N - 1; ++k) {
-        Glo_p[k] = Glo[IA + k] - sslo * R.al[k];
-        Glo[IA + k] = Glo[IA + k] - sslo * L.al[k];
+        for (int k = 0; k < N - 1; ++k) {
+            Glo_p[k] = Glo[IA + k] - ss * Rr.al[k];
+            Glo[IA + k] = Glo[IA + k] - ss * Lr.al[k];
+        }
     }
     if (P.flags & F_FIRST_ORDER) {
 #pragma unroll
@@ -88,23 +115,22 @@ __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, do
     }
 
     // App. D: projection with the midpoint means of alpha_k rho_k, rho and c
-    double arb[N];
+    R arb[N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) arb[k] = 0.5 * (L.ar[k] + R.ar[k]);
-    const double rb = 0.5 * (L.rho + R.rho), cb = 0.5 * (L.c + R.c);
-    const double irc = 1.0 / (rb * cb), irc2 = irc / cb;
+    for (int k = 0; k < N; ++k) arb[k] = (R)0.5 * (Lr.ar[k] + Rr.ar[k]);
+    const R rb = (R)0.5 * (Lr.rho + Rr.rho), cb = (R)0.5 * (Lr.c + Rr.c);
+    const R irc = (R)1 / (rb * cb), irc2 = irc / cb;
     const double eps = P.eps_weno;
-    double UL[M], UR[M], v[6];
+    R UL[M], UR[M], v[6];
 #pragma unroll
-    for (int j = 0; j < 6; ++j)
-        v[j] = nodev<NS, FS>(nd, j, F::U + DIR) - nodev<NS, FS>(nd, j, F::P) * irc;
-    weno_pair(v, eps, UL[0], UR[0]);
+    for (int j = 0; j < 6; ++j) v[j] = dv(j, F::U + DIR) - dv(j, F::P) * irc;
+    weno_pair<R>(v, eps, UL[0], UR[0]);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        const double s = arb[k] * irc2;
+        const R s = arb[k] * irc2;
 #pragma unroll
-        for (int j = 0; j < 6; ++j) v[j] = nodev<NS, FS>(nd, j, k) - s * nodev<NS, FS>(nd, j, F::P);
-        weno_pair(v, eps, UL[1 + k], UR[1 + k]);
+        for (int j = 0; j < 6; ++j) v[j] = dv(j, k) - s * dv(j, F::P);
+        weno_pair<R>(v, eps, UL[1 + k], UR[1 + k]);
     }
     {
         int t = 0;
@@ -112,62 +138,63 @@ __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, do
         for (int d = 0; d < D; ++d) {
             if (d == DIR) continue;
 #pragma unroll
-            for (int j = 0; j < 6; ++j) v[j] = nodev<NS, FS>(nd, j, F::U + d);
-            weno_pair(v, eps, UL[1 + N + t], UR[1 + N + t]);
+            for (int j = 0; j < 6; ++j) v[j] = dv(j, F::U + d);
+            weno_pair<R>(v, eps, UL[1 + N + t], UR[1 + N + t]);
             ++t;
         }
     }
 #pragma unroll
     for (int k = 0; k < N - 1; ++k) {
 #pragma unroll
-        for (int j = 0; j < 6; ++j) v[j] = nodev<NS, FS>(nd, j, IA + k);
-        weno_pair(v, eps, UL[N + D + k], UR[N + D + k]);
+        for (int j = 0; j < 6; ++j) v[j] = dv(j, IA + k);
+        weno_pair<R>(v, eps, UL[N + D + k], UR[N + D + k]);
     }
 #pragma unroll
-    for (int j = 0; j < 6; ++j)
-        v[j] = nodev<NS, FS>(nd, j, F::U + DIR) + nodev<NS, FS>(nd, j, F::P) * irc;
-    weno_pair(v, eps, UL[M - 1], UR[M - 1]);
+    for (int j = 0; j < 6; ++j) v[j] = dv(j, F::U + DIR) + dv(j, F::P) * irc;
+    weno_pair<R>(v, eps, UL[M - 1], UR[M - 1]);
 
     // back to primitive slots: V = R U
-    St<N, D> VL, VR;
-    const double h2c = 0.5 / cb, hrc = 0.5 * rb * cb;
+    St<N, D, R> VL, VR;
+    const R h2c = (R)0.5 / cb, hrc = (R)0.5 * rb * cb;
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
-        const double* U = side ? UR : UL;
-        St<N, D>& V = side ? VR : VL;
-        const double dU = U[M - 1] - U[0];
+        const R* U = side ? UR : UL;
+        St<N, D, R>& V = side ? VR : VL;
+        const R dU = U[M - 1] - U[0];
 #pragma unroll
-        for (int k = 0; k < N; ++k) V.ar[k] = U[1 + k] + arb[k] * h2c * dU;
+        for (int k = 0; k < N; ++k) V.ar[k] = back(k, U[1 + k] + arb[k] * h2c * dU);
         int t = 0;
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             if (d == DIR) {
-                V.u[d] = 0.5 * (U[0] + U[M - 1]);
+                V.u[d] = back(F::U + d, (R)0.5 * (U[0] + U[M - 1]));
             } else {
-                V.u[d] = U[1 + N + t];
+                V.u[d] = back(F::U + d, U[1 + N + t]);
                 ++t;
             }
         }
-        V.p = hrc * dU;
+        V.p = back(F::P, hrc * dU);
 #pragma unroll
-        for (int k = 0; k < N - 1; ++k) V.al[k] = U[N + D + k];
+        for (int k = 0; k < N - 1; ++k) V.al[k] = back_d(IA + k, U[N + D + k]);
     }
 
     // Sec. 4.3.2 interpolation limiter: left against node i, right against node i+1
     if (!(P.flags & F_NO_LIMITERS)) {
-        interp_limit<N, D>(e, P, VL, L, cnt);  // also completes the state
-        interp_limit<N, D>(e, P, VR, R, cnt);
+        interp_limit<N, D, R>(e, P, VL, Lr, cnt);  // also completes the state
+        interp_limit<N, D, R>(e, P, VR, Rr, cnt);
     } else {
-        complete_from_prim<N, D>(e, VL);
-        complete_from_prim<N, D>(e, VR);
+        complete_from_prim<N, D, R>(e, VL);
+        complete_from_prim<N, D, R>(e, VR);
     }
 
     // midpoint flux and velocity from HLLC on the interpolated states
     double Gt[M];
-    const double ut = hllc<N, D, DIR>(VL, VR, Gt);
+    const R ut = hllc<N, D, DIR, R>(VL, VR, Gt);
 
-    // shock sensor (Sec. 4.3.1) on mixture density and pressure
-    double sig = 0.0;
+    // shock sensor (Sec. 4.3.1) on mixture density and pressure, in double in
+    // both variants: C_s = 1e12 turns float rounding of p at a contact into
+    // a visible blending weight
+    R sig = 0;
     if (!(P.flags & F_NO_BLEND)) {
         double r[6], pr[6];
 #pragma unroll
@@ -175,49 +202,66 @@ __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, do
             r[j] = nodev<NS, FS>(nd, j, F::RHO);
             pr[j] = nodev<NS, FS>(nd, j, F::P);
         }
-        const double sr = 0.5 * (sensor_ratio(r[1], r[2], r[3], r[4], r[5]) + sensor_ratio(r[0], r[1], r[2], r[3], r[4]));
-        const double sp = 0.5 * (sensor_ratio(pr[1], pr[2], pr[3], pr[4], pr[5]) +
-                                 sensor_ratio(pr[0], pr[1], pr[2], pr[3], pr[4]));
+        const double sr = 0.5 * (sensor_ratio_t<double>(r[1], r[2], r[3], r[4], r[5]) +
+                                 sensor_ratio_t<double>(r[0], r[1], r[2], r[3], r[4]));
+        const double sp = 0.5 * (sensor_ratio_t<double>(pr[1], pr[2], pr[3], pr[4], pr[5]) +
+                                 sensor_ratio_t<double>(pr[0], pr[1], pr[2], pr[3], pr[4]));
         const double z = sr * sp;
         const double arg = P.Cs * (P.qexp == 2.0 ? z * z : pow(z, P.qexp));
         // tanh is exactly 0 at 0 and rounds to 1 for arguments >= 22
-        sig = arg == 0.0 ? 0.0 : (arg >= 22.0 ? 1.0 : tanh(arg));
+        sig = (R)(arg == 0.0 ? 0.0 : (arg >= 22.0 ? 1.0 : tanh(arg)));
     }
 
-    // HCS reconstruction (eq:reconstructed_G, eq:reconstructed_vel) and blending
-    const double psi = P.psi, ha = P.hcs_a, hb = P.hcs_b, hc = P.hcs_c;
-    double un[6], pj[6];
+    // HCS reconstruction (eq:reconstructed_G, eq:reconstructed_vel) and blending.
+    // Volume-fraction slots and the face velocity u-hat are double in both
+    // variants: G^+-_alpha = G_alpha - u-hat alpha_i cancels to (alpha-tilde -
+    // alpha_i) u-hat only if both terms see the same velocity at full precision.
+    const R psi = (R)P.psi, ha = (R)P.hcs_a, hb = (R)P.hcs_b, hc = (R)P.hcs_c;
+    const double psid = P.psi, had = P.hcs_a, hbd = P.hcs_b, hcd = P.hcs_c;
+    R un[6], pj[6];
+    double und[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-        un[j] = nodev<NS, FS>(nd, j, F::U + DIR);
-        pj[j] = nodev<NS, FS>(nd, j, F::P);
+        und[j] = nodev<NS, FS>(nd, j, F::U + DIR);
+        un[j] = (R)und[j];
+        pj[j] = nv(j, F::P);
     }
-    double Gho[M];
+    double Gho[M], Gho_p[NA];
+    const double sigd = sig;
 #pragma unroll
     for (int c = 0; c < M; ++c) {
-        double g[6];
+        if (c >= IA) {
+            double g[6];
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            const double w = nodev<NS, FS>(nd, j, c);
-            if (c >= N && c < N + D)
-                g[j] = w * un[j] + (c - N == DIR ? pj[j] : 0.0);
-            else if (c == IE)
-                g[j] = (w + pj[j]) * un[j];
-            else
-                g[j] = w * un[j];
+            for (int j = 0; j < 6; ++j) g[j] = nodev<NS, FS>(nd, j, c) * und[j];
+            const double ghcs = psid * Gt[c] - had * (g[2] + g[3]) + hbd * (g[1] + g[4]) - hcd * (g[0] + g[5]);
+            Gho[c] = sigd * Gt[c] + (1.0 - sigd) * ghcs;
+        } else {
+            R g[6];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                const R w = nv(j, c);
+                if (c >= N && c < N + D)
+                    g[j] = w * un[j] + (c - N == DIR ? pj[j] : (R)0);
+                else if (c == IE)
+                    g[j] = (w + pj[j]) * un[j];
+                else
+                    g[j] = w * un[j];
+            }
+            const R gt = (R)Gt[c];
+            const R ghcs = psi * gt - ha * (g[2] + g[3]) + hb * (g[1] + g[4]) - hc * (g[0] + g[5]);
+            Gho[c] = (double)(sig * gt + ((R)1 - sig) * ghcs);
         }
-        const double ghcs = psi * Gt[c] - ha * (g[2] + g[3]) + hb * (g[1] + g[4]) - hc * (g[0] + g[5]);
-        Gho[c] = sig * Gt[c] + (1.0 - sig) * ghcs;
     }
-    const double uhcs = psi * ut - ha * (un[2] + un[3]) + hb * (un[1] + un[4]) - hc * (un[0] + un[5]);
-    const double uh = sig * ut + (1.0 - sig) * uhcs;
+    const double utd = ut;
+    const double uhcs = psid * utd - had * (und[2] + und[3]) + hbd * (und[1] + und[4]) - hcd * (und[0] + und[5]);
+    const double uh = sigd * utd + (1.0 - sigd) * uhcs;
 
     // high-order quasi-conservative pair: alpha slots minus u-hat alpha_i / alpha_{i+1}
-    double Gho_p[NA];
 #pragma unroll
     for (int k = 0; k < N - 1; ++k) {
-        Gho_p[k] = Gho[IA + k] - uh * R.al[k];
-        Gho[IA + k] = Gho[IA + k] - uh * L.al[k];
+        Gho_p[k] = Gho[IA + k] - uh * Rr.al[k];
+        Gho[IA + k] = Gho[IA + k] - uh * Lr.al[k];
     }
     if (P.flags & F_NO_LIMITERS) {
 #pragma unroll
@@ -226,7 +270,7 @@ __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, do
         for (int k = 0; k < N - 1; ++k) Gp[k] = Gho_p[k];
         return;
     }
-    flux_limit<N, D, DIR>(e, P, L, R, lam, Gho, Gho_p, Glo, Glo_p, G, Gp, cnt);
+    flux_limit<N, D, DIR>(e, P, L, Rn, lam, Gho, Gho_p, Glo, Glo_p, G, Gp, cnt);
 }
 
 }  // namespace hrm

@@ -61,6 +61,70 @@ def algorithmic_bytes_per_cell_step(M):
     return 64 * M
 
 
+def batch_flops_per_step(batch):
+    """Algorithmic FP64 operations of one SSP-RK3 step of the whole ensemble:
+    per problem of n cells, the wavespeed pass (n nodes) and three stages of
+    n + 1 faces, n staged nodes and n final cell updates (1D, transmissive)."""
+    import numpy as np
+    N = batch.N
+    n = np.diff(batch.offsets).astype(np.float64)
+    per = n * node_flops(N, 1) + 3 * ((n + 1) * face_flops(N, 1) + n * (node_flops(N, 1) + cell_flops(N, 1, True)))
+    return float(per.sum())
+
+
+def bench_batch(args):
+    """Ensemble of 4096 1D two-phase Riemann problems (200-2000 cells): one
+    persistent launch per `steps_per_launch` steps, launch shape from the
+    autotuner; FP32 face arithmetic (the ensemble's stated precision) and the
+    FP64 path over the same number of steps for the speedup and L1 error."""
+    import numpy as np
+    import torch
+    from paper_2208_04488_amd import autotune, hrm
+    from paper_2208_04488_amd import inputs as I
+
+    batch = I.config4()
+    steps = args.batch_steps
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, prec in (("fp32", hrm.FP32), ("fp64", hrm.FP64)):
+        best = autotune.tune_batch(batch, precision=prec, use_cache=False)
+        k = best["steps_per_launch"]
+        nsteps = max(steps // k, 1) * k
+        s = hrm.BatchSolver(batch, precision=prec)
+        s.configure(best["threads"], best["blocks"], k)
+        s.run(k)  # captures the graph; these warm-up steps count in the state
+        torch.cuda.synchronize()
+        s.W.copy_(torch.from_numpy(batch.W))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        s.run(nsteps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        d = s.diagnostics()
+        res[name] = dict(ms=ms, steps=nsteps, W=s.state(), shape=best, relax_bad=d["relax_bad"],
+                         launches=nsteps // k)
+        s.close()
+    N = batch.N
+    r32, r64 = res["fp32"]["W"][:N].sum(axis=0), res["fp64"]["W"][:N].sum(axis=0)
+    l1 = float(np.abs(r32 - r64).sum() / np.abs(r64).sum())
+    flops = batch_flops_per_step(batch)
+    out = {"workload": f"{batch.nprob} independent 1D two-phase Riemann problems, {int(np.diff(batch.offsets).min())}"
+                       f"-{int(np.diff(batch.offsets).max())} cells ({batch.ncell} in total), transmissive, CFL 0.4",
+           "steps": res["fp32"]["steps"]}
+    for name in ("fp32", "fp64"):
+        r = res[name]
+        cups = batch.ncell * r["steps"] / (r["ms"] * 1e-3)
+        out[name] = {"value": cups, "unit": "cell-updates/s", "ms_per_step": r["ms"] / r["steps"],
+                     "launch_shape": {k: r["shape"][k] for k in ("threads", "blocks", "steps_per_launch")},
+                     "ms_per_launch": r["ms"] / r["launches"],
+                     "achieved_tflops_algorithmic": flops * r["steps"] / (r["ms"] * 1e-3) / 1e12,
+                     "relax_bad": r["relax_bad"]}
+    out["fp32"]["speedup_vs_fp64"] = out["fp32"]["value"] / out["fp64"]["value"]
+    out["fp32"]["l1_rel_rho_vs_fp64"] = l1
+    return out
+
+
 def cpu_baseline(prob, budget_s=12.0, max_steps=20):
     import oracle
     oracle.build(force=False)
@@ -88,6 +152,8 @@ def main():
     ap.add_argument("--nx", type=int, default=1024)
     ap.add_argument("--ny", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=1000,
+                    help="steps of the batched ensemble (0 skips it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 512 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -197,6 +263,8 @@ def main():
                    "ms_per_step": ms32 / args.steps,
                    "l1_rel_rho_vs_fp64": float(np.abs(rho32 - rho64).sum() / np.abs(rho64).sum()),
                    "after_steps": args.warmup + args.steps, "relax_bad": d32["relax_bad"]}
+    if args.batch_steps > 0:
+        out["batched"] = bench_batch(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)

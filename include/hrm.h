@@ -190,6 +190,49 @@ int hrm_set_timing(hrm_ctx* ctx, int mask);
  * totals restart from zero. */
 int hrm_get_timing(hrm_ctx* ctx, double* ms, long long* counts);
 
+/* ------------------------------------------------------------------------
+ * Ragged ensemble of independent 1D problems (the fractional algorithm of
+ * Sec. 4 applied to many shock tubes at once).  Problem b owns cells
+ * offsets[b] .. offsets[b+1]-1 of one structure-of-arrays state of
+ * T = offsets[nprob] cells, component-major: d_W[c * T + cell], c < M = 2N+1.
+ * Both ends of every problem are transmissive.  Every problem takes its own
+ * time step from its own maximum |u| + c (Sec. 4.1.2, CFL given per run) and
+ * keeps its own time.  One persistent launch advances every problem by
+ * `steps_per_launch` SSP-RK3 steps with the relaxation after each stage; the
+ * workgroups take problems from an atomic queue, longest first. */
+typedef struct hrm_batch hrm_batch;
+
+/* Validates the EOS (as hrm_create; N = 2 or 3), offsets (offsets[0] = 0,
+ * strictly increasing: every problem has at least one cell) and dx[b] > 0,
+ * all HOST arrays copied at creation; precision HRM_FP64 or HRM_FP32 (face
+ * arithmetic, as for grids).  Allocates two stage buffers of M x T doubles.
+ * prm may be NULL (paper parameters). */
+int hrm_batch_create(const hrm_eos* eos, const hrm_params* prm, int nprob, const long long* h_offsets,
+                     const double* h_dx, int precision, hrm_batch** out);
+int hrm_batch_destroy(hrm_batch* b);
+const char* hrm_batch_last_error(const hrm_batch* b);
+
+/* Launch shape: threads per workgroup (64, 128 or 256; one face per
+ * thread, tiles of threads-1 cells), workgroups of the persistent launch,
+ * and SSP-RK3 steps per launch.  Defaults 256, 512, 10.  A change drops the
+ * captured graph. */
+int hrm_batch_configure(hrm_batch* b, int threads, int blocks, int steps_per_launch);
+
+/* Advance every problem of d_W (device, M x T) in place by nsteps steps, a
+ * multiple of steps_per_launch.  The first call captures (queue reset,
+ * persistent launch) into a hipGraph on a private stream; calls with the
+ * same (d_W, cfl) replay it nsteps / steps_per_launch times on `stream`.
+ * Calls on one batch must not overlap (they share the stage buffers). */
+int hrm_batch_run(hrm_batch* b, double* d_W, int nsteps, double cfl, void* stream);
+
+/* Synchronise and copy the per-problem times (sum of the steps taken since
+ * creation) to h_t[nprob]. */
+int hrm_batch_time(hrm_batch* b, double* h_t);
+
+/* Synchronise and copy the counters (as hrm_get_diagnostics; counts every
+ * face of every problem once per stage). */
+int hrm_batch_get_diagnostics(hrm_batch* b, hrm_diag* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,7 +10,12 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhrm.so")
-SOURCES = ["hrm.hip"]
+SOURCES = ["hrm.hip", "hrm_batch.hip"]
+# per-source flags: the persistent batch kernel wraps the face arithmetic in
+# problem / step / stage / tile loops; machine-level loop-invariant code motion
+# would lift dozens of FP64 constant materialisations out of them and keep
+# them in vector registers for the whole launch (spills at two waves/SIMD)
+SOURCE_FLAGS = {"hrm_batch.hip": ["-mllvm", "-disable-machine-licm"]}
 ARCH = "gfx950"
 
 # -packed-fp32-ops: no v_pk_*_f32 from the compiler
@@ -29,7 +34,7 @@ def build(verbose: bool = False, extra=()) -> str:
     objs = []
     for src in SOURCES:
         obj = os.path.join(CSRC, src + ".o")
-        cmd = [hipcc(), *HIPFLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
+        cmd = [hipcc(), *HIPFLAGS, *SOURCE_FLAGS.get(src, []), *extra, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c",
                os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

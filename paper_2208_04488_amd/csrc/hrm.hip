@@ -45,25 +45,6 @@ struct SweepArgs {
 
 constexpr int MODE_WRITE = 0, MODE_ADD = 1, MODE_FINAL = 2;
 
-__device__ inline int map_bc(int g, int n, int lo, int hi)
-{
-    if (g < 0) return lo == HRM_BC_PERIODIC ? ((g % n) + n) % n : 0;
-    if (g >= n) return hi == HRM_BC_PERIODIC ? g % n : n - 1;
-    return g;
-}
-
-// sum each counter over the wave, one atomic per non-zero counter
-__device__ inline void flush_counters(const unsigned* c, unsigned long long* dst)
-{
-#pragma unroll
-    for (int k = 0; k < C_N; ++k) {
-        unsigned long long v = c[k];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (__lane_id() == 0 && v != 0ull) atomicAdd(&dst[k], v);
-    }
-}
-
 // Tile: BS face threads along the sweep direction (BS-1 cells), BA threads
 // across it.  DIR == 0: blockDim = (BS, BA), across = y, blockIdx.z = z.
 // DIR == 1: blockDim = (BA, BS), across = x, blockIdx.z = z.
@@ -137,7 +118,10 @@ __global__ void __launch_bounds__(BS* BA, 2) k_sweep(const SweepArgs A)
     {
         unsigned lc[C_N] = {0, 0, 0, 0, 0, 0, 0};
         face_flux<N, D, DIR, NS, FS, R>(lds + base(ta, ts), A.e, A.P, A.slot[1 + DIR], G, Gp, lc);
-        const bool ok = (c0 - 1 + ts <= nsw - 1) && (abase + ta < na);
+        // face c0+ts is counted once: the last face of a tile is the first
+        // face of the next tile unless it is the boundary face nsw
+        const int f = c0 + ts;
+        const bool ok = f <= nsw && (ts < BS - 1 || f == nsw) && (abase + ta < na);
         if (ok)
 #pragma unroll
             for (int k = 0; k < C_N; ++k) cnt[k] += lc[k];
@@ -201,27 +185,6 @@ __global__ void __launch_bounds__(256) k_relax(double* W, long long nc, EosDev e
         }
     }
     flush_counters(c, cnt);
-}
-
-// NaN-propagating max (a NaN anywhere makes the result NaN)
-__device__ inline double nmax(double a, double b) { return a != a ? a : (b != b ? b : fmax(a, b)); }
-
-template <int D>
-__device__ inline void block_max(double* m, double* sh)
-{
-#pragma unroll
-    for (int d = 0; d < D; ++d)
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) m[d] = nmax(m[d], __shfl_xor(m[d], off, 64));
-    const int w = threadIdx.x >> 6;
-    if (__lane_id() == 0)
-#pragma unroll
-        for (int d = 0; d < D; ++d) sh[w * D + d] = m[d];
-    __syncthreads();
-    if (threadIdx.x == 0)
-        for (int i = 1; i < (int)(blockDim.x >> 6); ++i)
-#pragma unroll
-            for (int d = 0; d < D; ++d) m[d] = nmax(m[d], sh[i * D + d]);
 }
 
 template <int N, int D>

@@ -488,6 +488,49 @@ __device__ inline void flux_limit(const EosDev& e, const ParDev& P, const St<N, 
     }
 }
 
+// ghost index map: transmissive copies the edge cell, periodic wraps
+__device__ inline int map_bc(int g, int n, int lo, int hi)
+{
+    if (g < 0) return lo == 1 ? ((g % n) + n) % n : 0;
+    if (g >= n) return hi == 1 ? g % n : n - 1;
+    return g;
+}
+
+// sum each counter over the wave, one atomic per non-zero counter
+__device__ inline void flush_counters(const unsigned* c, unsigned long long* dst)
+{
+#pragma unroll
+    for (int k = 0; k < C_N; ++k) {
+        unsigned long long v = c[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (__lane_id() == 0 && v != 0ull) atomicAdd(&dst[k], v);
+    }
+}
+
+// NaN-propagating max (a NaN anywhere makes the result NaN)
+__device__ inline double nmax(double a, double b) { return a != a ? a : (b != b ? b : fmax(a, b)); }
+
+// block-wide max of D values (blockDim.x a multiple of 64, <= 256); the
+// result is valid in thread 0; sh holds >= 4 * D doubles
+template <int D>
+__device__ inline void block_max(double* m, double* sh)
+{
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) m[d] = nmax(m[d], __shfl_xor(m[d], off, 64));
+    const int w = threadIdx.x >> 6;
+    if (__lane_id() == 0)
+#pragma unroll
+        for (int d = 0; d < D; ++d) sh[w * D + d] = m[d];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i)
+#pragma unroll
+            for (int d = 0; d < D; ++d) m[d] = nmax(m[d], sh[i * D + d]);
+}
+
 // Sec. 4.2 infinite-rate thermal relaxation of one cell (species 0 is the
 // only stiffened gas): A p^2 + B p + C = 0 (eq:Ap_Bp_Cp_1..3), positive root
 // (taken as 2C/(-B - sqrt) when B > 0), T from eq:T_relax_e, then

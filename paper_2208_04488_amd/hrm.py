@@ -58,6 +58,10 @@ class HrmError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    # torch first: the process then has one HIP runtime (torch's), which the
+    # library binds to; loading the library first would bring in a second one
+    # and torch would find no device
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, dp = ctypes.c_void_p, ctypes.c_double
     L.hrm_default_params.argtypes = [ctypes.POINTER(hrm_params)]
@@ -77,6 +81,16 @@ def _load():
     L.hrm_reset_diagnostics.argtypes = [vp, vp]
     L.hrm_set_timing.argtypes = [vp, ctypes.c_int]
     L.hrm_get_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
+    L.hrm_batch_create.argtypes = [ctypes.POINTER(hrm_eos), ctypes.POINTER(hrm_params), ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double),
+                                   ctypes.c_int, ctypes.POINTER(vp)]
+    L.hrm_batch_destroy.argtypes = [vp]
+    L.hrm_batch_last_error.argtypes = [vp]
+    L.hrm_batch_last_error.restype = ctypes.c_char_p
+    L.hrm_batch_configure.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.hrm_batch_run.argtypes = [vp, vp, ctypes.c_int, dp, vp]
+    L.hrm_batch_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.hrm_batch_get_diagnostics.argtypes = [vp, ctypes.POINTER(hrm_diag)]
     return L
 
 
@@ -191,6 +205,56 @@ def hrm_get_timing(ctx) -> dict:
     return {k: (ms[i], cnt[i]) for i, k in enumerate(TIMERS)}
 
 
+def _bcheck(b, rc):
+    if rc != HRM_OK:
+        msg = lib.hrm_batch_last_error(b).decode() if b else ""
+        raise HrmError(rc, msg)
+    return rc
+
+
+def hrm_batch_create(eos: hrm_eos, params: Optional[hrm_params], offsets, dx, precision=FP64) -> int:
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    dxa = np.ascontiguousarray(dx, dtype=np.float64)
+    nprob = len(off) - 1
+    if nprob < 1 or len(dxa) != nprob:
+        raise ValueError("offsets must have nprob + 1 entries and dx nprob")
+    b = ctypes.c_void_p()
+    rc = lib.hrm_batch_create(ctypes.byref(eos), ctypes.byref(params) if params else None, nprob,
+                              off.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)),
+                              dxa.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(precision), ctypes.byref(b))
+    if rc != HRM_OK:
+        raise HrmError(rc, "hrm_batch_create rejected the EOS/offsets/dx")
+    return b.value
+
+
+def hrm_batch_destroy(b: int) -> None:
+    _bcheck(None, lib.hrm_batch_destroy(b))
+
+
+def hrm_batch_configure(b, threads, blocks, steps_per_launch):
+    return _bcheck(b, lib.hrm_batch_configure(b, int(threads), int(blocks), int(steps_per_launch)))
+
+
+def hrm_batch_run(b, W, nsteps, cfl, stream=None):
+    return _bcheck(b, lib.hrm_batch_run(b, _ptr(W), int(nsteps), float(cfl), _stream(stream)))
+
+
+def hrm_batch_time(b, nprob) -> np.ndarray:
+    t = np.zeros(nprob, dtype=np.float64)
+    _bcheck(b, lib.hrm_batch_time(b, t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return t
+
+
+def hrm_batch_get_diagnostics(b) -> dict:
+    d = hrm_diag()
+    rc = lib.hrm_batch_get_diagnostics(b, ctypes.byref(d))
+    if rc not in (HRM_OK, HRM_EADMISSIBLE):
+        _bcheck(b, rc)
+    out = {k: int(getattr(d, k)) for k, _ in hrm_diag._fields_}
+    out["status"] = rc
+    return out
+
+
 # ------------------------------------------------------------- convenience
 def make_grid(D, n, dx, bc, precision=FP64, weights=WEIGHTS_IS, flags=0) -> hrm_grid:
     g = hrm_grid()
@@ -277,3 +341,44 @@ class Solver:
 
     def diagnostics(self):
         return hrm_get_diagnostics(self.ctx)
+
+
+class BatchSolver:
+    """A batch handle plus the device state of an ``inputs.Batch``."""
+
+    def __init__(self, batch, precision=FP64, params: Optional[hrm_params] = None, W=None):
+        import torch
+        self.torch = torch
+        self.batch = batch
+        e = batch.eos
+        self.eos = make_eos(e.gamma, e.cv, e.pinf, e.q)
+        self.b = hrm_batch_create(self.eos, params, batch.offsets, batch.dx, precision)
+        self.W = torch.from_numpy(np.ascontiguousarray(batch.W if W is None else W)).to(torch.device("cuda"))
+        self.steps_per_launch = 10
+
+    def configure(self, threads, blocks, steps_per_launch):
+        hrm_batch_configure(self.b, threads, blocks, steps_per_launch)
+        self.steps_per_launch = steps_per_launch
+
+    def run(self, nsteps, cfl=None):
+        hrm_batch_run(self.b, self.W, nsteps, self.batch.cfl if cfl is None else cfl)
+
+    def state(self) -> np.ndarray:
+        return self.W.cpu().numpy()
+
+    def times(self) -> np.ndarray:
+        return hrm_batch_time(self.b, self.batch.nprob)
+
+    def diagnostics(self):
+        return hrm_batch_get_diagnostics(self.b)
+
+    def close(self):
+        if self.b:
+            hrm_batch_destroy(self.b)
+            self.b = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

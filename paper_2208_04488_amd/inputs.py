@@ -406,3 +406,78 @@ def random_admissible(eos: EOS, D: int, count: int, seed: int, p_range=(1e4, 1e9
         a[major, np.arange(count)] = 1.0 - (N - 1) * TRACE
     u = [rng.normal(0.0, u_scale, count) for _ in range(D)]
     return equilibrium_state(eos, list(a), u, p, T)
+
+
+@dataclass
+class Batch:
+    """Ragged ensemble of independent 1D problems stored back to back:
+    W is (M, T) with T = offsets[-1]; problem b owns cells offsets[b]..offsets[b+1]-1."""
+    name: str
+    eos: EOS
+    W: np.ndarray
+    offsets: np.ndarray
+    dx: np.ndarray
+    cfl: float = 0.4
+    nsteps: int = 1000
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def N(self) -> int:
+        return self.eos.N
+
+    @property
+    def M(self) -> int:
+        return 2 * self.eos.N + 1
+
+    @property
+    def nprob(self) -> int:
+        return len(self.offsets) - 1
+
+    @property
+    def ncell(self) -> int:
+        return int(self.offsets[-1])
+
+    def problem(self, b: int) -> Problem:
+        """Problem b on its own grid (same inputs), for comparisons."""
+        lo, hi = int(self.offsets[b]), int(self.offsets[b + 1])
+        n = hi - lo
+        W = np.ascontiguousarray(self.W[:, lo:hi].reshape(self.M, 1, 1, n))
+        return Problem(f"{self.name}[{b}]", self.eos, 1, (n,), (float(self.dx[b]),),
+                       [(TRANSMISSIVE, TRANSMISSIVE)], W, cfl=self.cfl, x0=(0.0,))
+
+
+def config4(nprob=4096, nmin=200, nmax=2000, seed=4001, lengths=None):
+    """Batched ensemble of two-phase Riemann problems on [0, 1] with the
+    interface at 0.5: lengths uniform in [nmin, nmax]; per side p log-uniform
+    in [1e5, 1e9] Pa, majority density log-uniform in [1, 1000] kg/m^3, the
+    majority species liquid (gamma 4.4, pinf 6e8) or air with probability 1/2;
+    traces 1e-8 at the side's temperature; u = 0; transmissive; CFL 0.4.
+    `lengths`, if given, fixes the problem lengths (and their number)."""
+    eos = eos_of(LIQ_A, AIR)
+    rng = np.random.default_rng(seed)
+    if lengths is not None:
+        lens = np.asarray(lengths, dtype=np.int64)
+        nprob = len(lens)
+    else:
+        lens = rng.integers(nmin, nmax + 1, size=nprob)
+    offsets = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    parts, dxs = [], []
+    for b in range(nprob):
+        n = int(lens[b])
+        sides = []
+        for _ in range(2):
+            p = float(np.exp(rng.uniform(np.log(1e5), np.log(1e9))))
+            rho = float(np.exp(rng.uniform(np.log(1.0), np.log(1000.0))))
+            major = int(rng.integers(0, 2))
+            sides.append(_side(eos, major, p, rho))
+        dx = 1.0 / n
+        x = (np.arange(n) + 0.5) * dx
+        left = x < 0.5
+        L, R = sides
+        alpha = [np.where(left, L[0][k], R[0][k]) for k in range(2)]
+        rho_k = [np.where(left, L[1][k], R[1][k]) for k in range(2)]
+        p = np.where(left, L[3], R[3])
+        parts.append(state_from_fields(eos, alpha, rho_k, [np.zeros(n)], p))
+        dxs.append(dx)
+    W = np.ascontiguousarray(np.concatenate(parts, axis=1))
+    return Batch("config4_batched", eos, W, offsets, np.asarray(dxs), meta=dict(seed=seed))

@@ -68,3 +68,47 @@ def test_null_context_is_rejected(H):
     assert H.lib.hrm_relax(None, None, None) == H.HRM_EINVAL
     assert H.lib.hrm_rk_stage(None, 0, None, None, None, None, None) == H.HRM_EINVAL
     assert H.lib.hrm_destroy(None) == H.HRM_EINVAL
+
+
+@pytest.mark.parametrize("case", ["nprob0", "first_offset", "empty_problem", "decreasing", "dx0", "dx_nan",
+                                  "species1", "species4", "second_liquid", "precision"])
+def test_batch_create_rejects_bad_input(H, case):
+    import numpy as np
+    e = _eos(H)
+    off = np.array([0, 10, 30, 35], dtype=np.int64)
+    dx = np.array([0.1, 0.05, 0.2])
+    nprob, prec = 3, H.FP64
+    if case == "nprob0":
+        nprob = 0
+    elif case == "first_offset":
+        off[0] = 1
+    elif case == "empty_problem":
+        off[2] = 10
+    elif case == "decreasing":
+        off[2] = 5
+    elif case == "dx0":
+        dx[1] = 0.0
+    elif case == "dx_nan":
+        dx[2] = float("nan")
+    elif case == "species1":
+        e.nspecies = 1
+    elif case == "species4":
+        e = H.make_eos([4.4, 1.4, 1.67, 1.3], [954.5, 719.3, 3110.0, 700.0], [6e8, 0, 0, 0], [0, 0, 0, 0])
+    elif case == "second_liquid":
+        e = _eos(H, pinf1=1e8)
+    elif case == "precision":
+        prec = 7
+    b = ctypes.c_void_p(123)
+    rc = H.lib.hrm_batch_create(ctypes.byref(e), None, nprob,
+                                off.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)),
+                                dx.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), prec, ctypes.byref(b))
+    assert rc in (H.HRM_EINVAL, H.HRM_EUNSUPPORTED)
+    assert rc == (H.HRM_EUNSUPPORTED if case == "species4" else H.HRM_EINVAL)
+    assert b.value is None
+
+
+def test_null_batch_is_rejected(H):
+    assert H.lib.hrm_batch_destroy(None) == H.HRM_EINVAL
+    assert H.lib.hrm_batch_configure(None, 256, 512, 10) == H.HRM_EINVAL
+    assert H.lib.hrm_batch_run(None, None, 10, 0.4, None) == H.HRM_EINVAL
+    assert H.lib.hrm_batch_last_error(None) == b"NULL batch"

@@ -47,18 +47,23 @@ def rel_err(A, B, N, D, cmax):
     return (np.abs(A - B).reshape(M, -1).max(axis=1) / s).max()
 
 
-def solver(H, prob, flags, W=None):
-    return H.Solver(prob, flags=flags, W=W)
+def solver(H, prob, flags, W=None, params=None):
+    hp = None
+    if params:
+        hp = H.hrm_default_params()
+        for k, v in params.items():
+            setattr(hp, k, v)
+    return H.Solver(prob, flags=flags, W=W, params=hp)
 
 
-def check_stages(H, orc, prob, W0, flags=0, relax=True, tol=TOL, counters=True):
+def check_stages(H, orc, prob, W0, flags=0, relax=True, tol=TOL, counters=True, params=None):
     """Three SSP-RK3 stages from the same inputs on both sides."""
     import torch
     N, D = prob.N, prob.D
-    o = orc.from_problem(prob, flags=flags & 7)
+    o = orc.from_problem(prob, flags=flags & 7, **(params or {}))
     dt, lam = o.dt(W0, prob.cfl)
     cmax = o.max_wavespeed(W0).max()
-    s = solver(H, prob, (flags & 7) | (H.FUSE_RELAX if relax else 0), W=W0)
+    s = solver(H, prob, (flags & 7) | (H.FUSE_RELAX if relax else 0), W=W0, params=params)
     s.set_slot(dt, lam)
     Wn = s.W.clone()
     Ws = Wn
@@ -309,3 +314,16 @@ def test_graph_replay_matches_eager(H, orc):
         assert torch.equal(g.slot, e.slot), k
     g.close()
     e.close()
+
+
+# every face is counted once, including a face shared by two tiles of the
+# sweep: at 364 cells the config-1 interface (x = 0.7) sits on face 255, the
+# face shared by the first two 255-cell tiles of the 1D sweep, and the flux
+# limiter acts there; at 130 x 70 the column's interface crosses the
+# boundaries of the 15-row tiles of the y sweep where limiters act (rows 45)
+@pytest.mark.parametrize("maker", ["config1_364", "config2_130x70"])
+def test_counters_at_tile_seams(H, orc, maker):
+    prob = {"config1_364": lambda: I.config1(364), "config2_130x70": lambda: I.config2(130, 70)}[maker]()
+    W0 = developed(orc, prob, 3)
+    cnt = check_stages(H, orc, prob, W0)
+    assert cnt["alg1"] + cnt["alg2"] + cnt["alg3"] + cnt["alg4"] > 0, cnt

@@ -233,23 +233,46 @@ __device__ inline R hllc(const St<N, D, R>& L, const St<N, D, R>& Rs, double* G)
     const R sg = ss > (R)0 ? (R)1 : (ss < (R)0 ? (R)-1 : (R)0);
     const R wl = (R)0.5 * ((R)1 + sg), wr = (R)0.5 * ((R)1 - sg);
     const R sm = fmin((R)0, sL), sp = fmax((R)0, sR);
-    const R chiL = dL / (sL - ss), chiR = dR / (sR - ss);
+    if constexpr (sizeof(R) == sizeof(double)) {
+        // star states U*_K = chi_K (...) with chi_K = (s_K - u_K) / (s_K - s*)
+        const R chiL = dL / (sL - ss), chiR = dR / (sR - ss);
 #pragma unroll
-    for (int k = 0; k < N; ++k)
-        G[k] = wl * (L.ar[k] * uL + sm * (chiL * L.ar[k] - L.ar[k])) +
-               wr * (Rs.ar[k] * uR + sp * (chiR * Rs.ar[k] - Rs.ar[k]));
+        for (int k = 0; k < N; ++k)
+            G[k] = wl * (L.ar[k] * uL + sm * (chiL * L.ar[k] - L.ar[k])) +
+                   wr * (Rs.ar[k] * uR + sp * (chiR * Rs.ar[k] - Rs.ar[k]));
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-        const R FLd = L.mom[d] * uL + (d == DIR ? L.p : (R)0);
-        const R FRd = Rs.mom[d] * uR + (d == DIR ? Rs.p : (R)0);
-        const R WsL = d == DIR ? chiL * L.rho * ss : chiL * L.rho * L.u[d];
-        const R WsR = d == DIR ? chiR * Rs.rho * ss : chiR * Rs.rho * Rs.u[d];
-        G[N + d] = wl * (FLd + sm * (WsL - L.mom[d])) + wr * (FRd + sp * (WsR - Rs.mom[d]));
-    }
-    {
+        for (int d = 0; d < D; ++d) {
+            const R FLd = L.mom[d] * uL + (d == DIR ? L.p : (R)0);
+            const R FRd = Rs.mom[d] * uR + (d == DIR ? Rs.p : (R)0);
+            const R WsL = d == DIR ? chiL * L.rho * ss : chiL * L.rho * L.u[d];
+            const R WsR = d == DIR ? chiR * Rs.rho * ss : chiR * Rs.rho * Rs.u[d];
+            G[N + d] = wl * (FLd + sm * (WsL - L.mom[d])) + wr * (FRd + sp * (WsR - Rs.mom[d]));
+        }
         const R EsL = chiL * (L.E + (ss - uL) * (L.rho * ss + L.p / dL));
         const R EsR = chiR * (Rs.E + (ss - uR) * (Rs.rho * ss + Rs.p / dR));
         G[IE] = wl * ((L.E + L.p) * uL + sm * (EsL - L.E)) + wr * ((Rs.E + Rs.p) * uR + sp * (EsR - Rs.E));
+    } else {
+        // float: the jumps U*_K - U_K in closed form.  chi_K - 1 =
+        // (s* - u_K) / (s_K - s*) is far below float resolution when |s_K|
+        // (a liquid's sound speed) dwarfs |s* - u_K|; chi_K U_K - U_K would
+        // then round to 0 and drop the star-state correction of the flux.
+        const R qL = (ss - uL) / (sL - ss), qR = (ss - uR) / (sR - ss);
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+            G[k] = wl * (L.ar[k] * uL + sm * (qL * L.ar[k])) + wr * (Rs.ar[k] * uR + sp * (qR * Rs.ar[k]));
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const R FLd = L.mom[d] * uL + (d == DIR ? L.p : (R)0);
+            const R FRd = Rs.mom[d] * uR + (d == DIR ? Rs.p : (R)0);
+            // chi (rho s*) - rho u = rho s_K q_K along DIR; chi m_d - m_d = q_K m_d across
+            const R JL = d == DIR ? L.rho * sL * qL : qL * L.mom[d];
+            const R JR = d == DIR ? Rs.rho * sR * qR : qR * Rs.mom[d];
+            G[N + d] = wl * (FLd + sm * JL) + wr * (FRd + sp * JR);
+        }
+        // E*_K - E_K = q_K (E_K + p_K + rho_K s* (s_K - u_K))
+        const R JL = qL * (L.E + L.p + L.rho * ss * dL);
+        const R JR = qR * (Rs.E + Rs.p + Rs.rho * ss * dR);
+        G[IE] = wl * ((L.E + L.p) * uL + sm * JL) + wr * ((Rs.E + Rs.p) * uR + sp * JR);
     }
 #pragma unroll
     for (int k = 0; k < N - 1; ++k)

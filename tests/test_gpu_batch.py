@@ -187,3 +187,36 @@ def test_batch_rejects_bad_runs(H, I):
     torch.cuda.synchronize()
     assert np.isfinite(s.state()).all()
     s.close()
+
+
+def test_fp32_light_liquid_contact_stays_positive(H, I):
+    """Problem 1381 of the ensemble: a liquid of density 3 kg/m^3 (sound speed
+    3e4 m/s) against air of density 99 kg/m^3 at nearly equal pressure.  The
+    HLLC wave-speed bound from the liquid side is 1e8 times the contact speed,
+    so in float the star-state jump of the air's partial density must be
+    formed in closed form; formed as chi U - U it rounds to zero, the
+    first-order flux loses its positivity and the trace density in the liquid
+    goes negative after a few hundred steps."""
+    full = I.config4()
+    b = 1381
+    lo, hi = int(full.offsets[b]), int(full.offsets[b + 1])
+    one = I.Batch("p1381", full.eos, np.ascontiguousarray(full.W[:, lo:hi]), np.array([0, hi - lo], dtype=np.int64),
+                  np.array([full.dx[b]]))
+    w64, _, d64 = run_batch(H, one, 400, shape=(256, 1, 20))
+    w32, _, d32 = run_batch(H, one, 400, precision=H.FP32, shape=(256, 1, 20))
+    N = one.N
+    assert d32["relax_bad"] == 0 and d64["relax_bad"] == 0
+    assert w32[:N].min() > 0.0, w32[:N].min()
+    r64, r32 = w64[:N].sum(axis=0), w32[:N].sum(axis=0)
+    assert np.abs(r32 - r64).sum() / np.abs(r64).sum() <= 1e-5
+
+
+def test_fp32_ensemble_positivity(H, I):
+    """The full FP32 ensemble over 300 steps: no relaxation failure, partial
+    densities and volume fractions stay positive."""
+    batch = I.config4()
+    w, t, d = run_batch(H, batch, 300, precision=H.FP32, shape=(256, 512, 20))
+    N = batch.N
+    assert d["relax_bad"] == 0, d
+    assert w[:N].min() > 0.0
+    assert w[N + 2:].min() > 0.0 and w[N + 2:].max() < 1.0

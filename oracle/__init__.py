@@ -59,7 +59,11 @@ class Setup(ctypes.Structure):
         ("hs_f_ar", ctypes.c_double), ("hs_f_a", ctypes.c_double), ("hs_f_re", ctypes.c_double),
         ("Cs", ctypes.c_double), ("qexp", ctypes.c_double), ("psi", ctypes.c_double),
         ("flags", ctypes.c_int),
+        ("weights", ctypes.c_int), ("mlp", ctypes.POINTER(ctypes.c_double)),
     ]
+
+W_IS, W_MLP = 0, 1
+MLP_NPARAM = 1347
 
 
 _lib = None
@@ -86,6 +90,10 @@ def lib():
         L.orc_cons_from_prim.argtypes = [sp, dp, dp]
         L.orc_weno.argtypes = [dp, ctypes.c_double]
         L.orc_weno.restype = ctypes.c_double
+        L.orc_mlp_interp.argtypes = [dp, dp, dp, dp]
+        L.orc_mlp_interp.restype = ctypes.c_int
+        L.orc_bf16.argtypes = [ctypes.c_double]
+        L.orc_bf16.restype = ctypes.c_double
         L.orc_sensor.argtypes = [dp]
         L.orc_sensor.restype = ctypes.c_double
         L.orc_hllc.argtypes = [sp, ctypes.c_int, dp, dp, dp]
@@ -121,7 +129,7 @@ class Oracle:
     State arrays are float64 of shape (M, nz, ny, nx), M = 2N + D.
     """
 
-    def __init__(self, N, D, n, dx, bc, gamma, cv, pinf, q, flags=0, **params):
+    def __init__(self, N, D, n, dx, bc, gamma, cv, pinf, q, flags=0, mlp=None, **params):
         s = Setup()
         s.N, s.D = N, D
         nn = list(n) + [1] * (3 - len(n))
@@ -138,6 +146,11 @@ class Oracle:
         for key, val in p.items():
             setattr(s, key, float(val))
         s.flags = int(flags)
+        if mlp is not None:
+            # learned weights: the parameters stay referenced by this object
+            self._mlp = _f64(mlp).copy()
+            assert self._mlp.size == MLP_NPARAM
+            s.weights, s.mlp = W_MLP, _dp(self._mlp)
         self.s = s
         self.N, self.D, self.M = N, D, 2 * N + D
         self.shape = (self.M, nn[2], nn[1], nn[0])
@@ -279,6 +292,20 @@ def weno(u5, eps=1e-15) -> float:
     return lib().orc_weno(_dp(_f64(u5)), float(eps))
 
 
+def mlp_interp(params, u5):
+    """Learned interpolation of one stencil (u_{i-2}..u_{i+2}): (value, omega),
+    value None if a weight is not finite (the caller then uses App. C)."""
+    out = np.zeros(1)
+    om = np.zeros(3)
+    ok = lib().orc_mlp_interp(_dp(_f64(params)), _dp(_f64(u5)), _dp(out), _dp(om))
+    return (float(out[0]) if ok else None), om
+
+
+def bf16(x) -> float:
+    """x rounded to float, then to bfloat16 (ties to even)."""
+    return lib().orc_bf16(float(x))
+
+
 def sensor(u6) -> float:
     return lib().orc_sensor(_dp(_f64(u6)))
 
@@ -289,7 +316,8 @@ def hcs_coeffs(psi=256.0 / 175.0):
     return out
 
 
-def from_problem(prob, flags=0, **params) -> Oracle:
+def from_problem(prob, flags=0, mlp=None, **params) -> Oracle:
     """An Oracle for a problem description from the input module (plain numbers only)."""
     e = prob.eos
-    return Oracle(prob.N, prob.D, prob.n, prob.dx, prob.bc, e.gamma, e.cv, e.pinf, e.q, flags=flags, **params)
+    return Oracle(prob.N, prob.D, prob.n, prob.dx, prob.bc, e.gamma, e.cv, e.pinf, e.q, flags=flags, mlp=mlp,
+                  **params)

@@ -64,7 +64,12 @@ typedef struct {
     double hs_f_ar, hs_f_a, hs_f_re;  /* flux hard switch: 1e-11, 1e-11, 1e-9 */
     double Cs, qexp, psi;             /* sensor C_s = 1e12, q = 2; HCS psi = 256/175 */
     int flags;
+    int weights;                      /* ORC_W_IS (App. C) or ORC_W_MLP (learned weights) */
+    const double *mlp;                /* ORC_W_MLP: the 1347 network parameters */
 } orc_setup;
+
+#define ORC_W_IS 0
+#define ORC_W_MLP 1
 
 /* one node (or interpolated face state) with the quantities of Sec. 2 */
 typedef struct {
@@ -231,6 +236,90 @@ static double hllc(const orc_setup *s, int n, const orc_state *L, const orc_stat
     for (int k = 0; k < N - 1; ++k)
         G[IAL(s, k)] = 0.5 * (1.0 + sg) * (L->alpha[k] * sstar) + 0.5 * (1.0 - sg) * (R->alpha[k] * sstar);
     return sstar;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Learned nonlinear weights (an extension of the method, not in the paper).  */
+/* The interpolant at i+1/2 is a convex combination of the three 3-point      */
+/* candidates of the fifth-order interpolation from u_{i-2..i+2}:             */
+/*   S_l = (3u_{i-2} - 10u_{i-1} + 15u_i)/8,  S_c = (-u_{i-1} + 6u_i + 3u_{i+1})/8, */
+/*   S_r = (3u_i + 6u_{i+1} - u_{i+2})/8,                                      */
+/* whose linear weights d = (1/16, 10/16, 5/16) give the fifth-order value.   */
+/* A perceptron 5-32-32-3 (ReLU) maps the normalised stencil                 */
+/*   x_j = (u_j - u_i) / max_j |u_j - u_i|      (x = 0 if the maximum is 0)    */
+/* to logits z, and omega = softmax(z + ln d): a zero last layer gives the    */
+/* linear weights.  Parameters, as 1347 numbers in this order: W1[5][32],     */
+/* b1[32], W2[32][32], b2[32], W3[32][3], b3[3] (row = input unit).           */
+/* The number formats are those of a bfloat16 matrix-core evaluation with     */
+/* float accumulation: inputs, W1, b1, W2, W3 and both hidden activations     */
+/* (after the ReLU) are rounded to bfloat16 (through float, to nearest even); */
+/* b2 and b3 are float; the sums themselves are taken in double here.         */
+/* ------------------------------------------------------------------------ */
+#define ORC_MLP_NPARAM 1347
+
+/* round to float, then to bfloat16 (8 significant bits), ties to even */
+static double bf16_round(double x)
+{
+    float f = (float)x;
+    unsigned int u;
+    memcpy(&u, &f, sizeof(u));
+    if ((u & 0x7f800000u) == 0x7f800000u) return (double)f; /* inf, NaN */
+    u += 0x7fffu + ((u >> 16) & 1u);
+    u &= 0xffff0000u;
+    memcpy(&f, &u, sizeof(f));
+    return (double)f;
+}
+
+static double to_float(double x) { return (double)(float)x; }
+
+/* omega[3] for the normalised stencil x[5] */
+static void mlp_weights(const double *P, const double *x, double *omega)
+{
+    const double *W1 = P, *b1 = P + 160, *W2 = P + 192, *b2 = P + 1216, *W3 = P + 1248, *b3 = P + 1344;
+    double xb[5], h1[32], h2[32], z[3];
+    for (int j = 0; j < 5; ++j) xb[j] = bf16_round(x[j]);
+    for (int h = 0; h < 32; ++h) {
+        double a = bf16_round(b1[h]);
+        for (int j = 0; j < 5; ++j) a += xb[j] * bf16_round(W1[j * 32 + h]);
+        h1[h] = bf16_round(a > 0.0 ? a : 0.0);
+    }
+    for (int h = 0; h < 32; ++h) {
+        double a = to_float(b2[h]);
+        for (int g = 0; g < 32; ++g) a += h1[g] * bf16_round(W2[g * 32 + h]);
+        h2[h] = bf16_round(a > 0.0 ? a : 0.0);
+    }
+    for (int k = 0; k < 3; ++k) {
+        double a = to_float(b3[k]);
+        for (int h = 0; h < 32; ++h) a += h2[h] * bf16_round(W3[h * 3 + k]);
+        z[k] = a;
+    }
+    const double lnd[3] = {log(1.0 / 16.0), log(10.0 / 16.0), log(5.0 / 16.0)};
+    double m = z[0] + lnd[0];
+    for (int k = 1; k < 3; ++k) m = fmax(m, z[k] + lnd[k]);
+    double e[3], sum = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        e[k] = exp(z[k] + lnd[k] - m);
+        sum += e[k];
+    }
+    for (int k = 0; k < 3; ++k) omega[k] = e[k] / sum;
+}
+
+/* learned interpolation of u = (u_{i-2}..u_{i+2}); returns 0 (and leaves
+ * *out alone) if a weight is not finite, so that the caller falls back */
+static int mlp_interp(const double *P, const double *u, double *out, double *omega)
+{
+    double s = 0.0;
+    for (int j = 0; j < 5; ++j) s = fmax(s, fabs(u[j] - u[2]));
+    double x[5];
+    for (int j = 0; j < 5; ++j) x[j] = s > 0.0 ? (u[j] - u[2]) / s : 0.0;
+    mlp_weights(P, x, omega);
+    for (int k = 0; k < 3; ++k)
+        if (!isfinite(omega[k])) return 0;
+    const double sl = (3.0 * u[0] - 10.0 * u[1] + 15.0 * u[2]) / 8.0;
+    const double sc = (-u[1] + 6.0 * u[2] + 3.0 * u[3]) / 8.0;
+    const double sr = (3.0 * u[2] + 6.0 * u[3] - u[4]) / 8.0;
+    *out = omega[0] * sl + omega[1] * sc + omega[2] * sr;
+    return 1;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -540,8 +629,10 @@ static void face_flux(const orc_setup *s, int n, const orc_state *nodes, double 
     for (int m = 0; m < M; ++m) {
         const double l5[5] = {U[0][m], U[1][m], U[2][m], U[3][m], U[4][m]};
         const double r5[5] = {U[5][m], U[4][m], U[3][m], U[2][m], U[1][m]};
-        UL[m] = weno_is(l5, s->eps_weno);
-        UR[m] = weno_is(r5, s->eps_weno);
+        double om[3];
+        /* learned weights, with App. C as the fallback for non-finite weights */
+        if (s->weights != ORC_W_MLP || !mlp_interp(s->mlp, l5, &UL[m], om)) UL[m] = weno_is(l5, s->eps_weno);
+        if (s->weights != ORC_W_MLP || !mlp_interp(s->mlp, r5, &UR[m], om)) UR[m] = weno_is(r5, s->eps_weno);
     }
     double VL[ORC_MAXM], VR[ORC_MAXM];
     matvec(M, Rm, UL, VL);
@@ -845,6 +936,15 @@ void orc_cons_from_prim(const orc_setup *s, const double *V, double *W)
 }
 
 double orc_weno(const double *u5, double eps) { return weno_is(u5, eps); }
+
+/* learned interpolation of one stencil; omega[3] receives the weights;
+ * returns 0 if they are not finite (*out then untouched) */
+int orc_mlp_interp(const double *params, const double *u5, double *out, double *omega)
+{
+    return mlp_interp(params, u5, out, omega);
+}
+
+double orc_bf16(double x) { return bf16_round(x); }
 
 double orc_sensor(const double *u6) { return sensor_sigma(u6); }
 

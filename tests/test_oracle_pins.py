@@ -624,3 +624,137 @@ def test_oracle_threads_do_not_change_results(orc):
     o.set_threads(4)
     b, _ = o.step(pr.W)
     assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------- learned weights
+# The learned variant is an extension (the paper's weights are App. C); its
+# oracle is pinned to what the mathematics fixes: the fifth-order linear
+# scheme when the last layer is zero, convexity, invariance under u -> a u + b,
+# back-propagation against finite differences, and the injection geometry.
+
+def _mlp():
+    from oracle import mlp_ref
+    return mlp_ref
+
+
+def test_mlp_zero_last_layer_is_fifth_order(orc):
+    M = _mlp()
+    p = M.init(5, last_scale=0.0)
+    rng = np.random.default_rng(1)
+    xs = np.arange(-2.0, 3.0)
+    for _ in range(20):
+        c = rng.normal(size=5)
+        P = np.polynomial.Polynomial(c)          # degree 4: the 5-point interpolation is exact
+        u5 = P(xs)
+        val, w = M.interp(p, u5[None, :])
+        assert np.allclose(w, M.LIN, rtol=0, atol=1e-15)
+        assert abs(val[0] - P(0.5)) <= 1e-12 * np.abs(u5).max()
+        cv, cw = orc.mlp_interp(p, u5)           # bfloat16 evaluation: z = 0 exactly as well
+        assert np.allclose(cw, M.LIN, rtol=0, atol=1e-15) and abs(cv - P(0.5)) <= 1e-12 * np.abs(u5).max()
+
+
+def test_mlp_candidates_are_third_order():
+    M = _mlp()
+    xs = np.arange(-2.0, 3.0)
+    for c in ([1, 0, 0], [0, 1, 0], [0, 0, 1], [0.3, -2, 1.7]):
+        P = np.polynomial.Polynomial(c)
+        for k, support in enumerate(([0, 1, 2], [1, 2, 3], [2, 3, 4])):
+            assert abs(M.CAND[k] @ P(xs) - P(0.5)) < 1e-13
+            assert set(np.nonzero(M.CAND[k])[0]) == set(support)
+
+
+def test_mlp_weights_convex_and_value_in_hull(orc):
+    M = _mlp()
+    p = M.init(7, last_scale=3.0)
+    rng = np.random.default_rng(2)
+    U = rng.normal(size=(400, 5)) * rng.lognormal(size=(400, 1)) * 10
+    val, w = M.interp(p, U)
+    assert (w >= 0).all() and np.allclose(w.sum(axis=1), 1.0, atol=1e-14)
+    S = U @ M.CAND.T
+    assert (val >= S.min(axis=1) - 1e-12 * np.abs(U).max()).all()
+    assert (val <= S.max(axis=1) + 1e-12 * np.abs(U).max()).all()
+    for u in U[:50]:
+        cv, cw = orc.mlp_interp(p, u)
+        assert (cw >= 0).all() and abs(cw.sum() - 1) < 1e-14
+        s = M.CAND @ u
+        assert s.min() - 1e-12 * np.abs(u).max() <= cv <= s.max() + 1e-12 * np.abs(u).max()
+
+
+def test_mlp_affine_invariance(orc):
+    M = _mlp()
+    p = M.init(8, last_scale=2.0)
+    rng = np.random.default_rng(3)
+    U = rng.normal(size=(100, 5))
+    v0, _ = M.interp(p, U)
+    v1, _ = M.interp(p, 3.7 * U - 12.5)
+    assert np.allclose(v1, 3.7 * v0 - 12.5, rtol=0, atol=1e-12)
+    # power-of-two scaling leaves the normalised inputs bit-identical
+    for u in U[:30]:
+        a, _ = orc.mlp_interp(p, u)
+        b, _ = orc.mlp_interp(p, 8.0 * u)
+        assert b == 8.0 * a
+
+
+def test_mlp_backprop_matches_finite_differences():
+    M = _mlp()
+    p = M.init(9, last_scale=1.0)
+    rng = np.random.default_rng(4)
+    X, _ = M.normalise(rng.normal(size=(300, 5)))
+    T = rng.uniform(-1, 1, size=300)
+    g = M.grad(p, X, T)
+    idx = list(range(0, 160, 7)) + list(range(160, 192, 5)) + list(range(192, 1216, 37)) + \
+        list(range(1216, 1248, 3)) + list(range(1248, 1347))
+    fd = M.fd_grad(p, X, T, h=1e-6, idx=idx)
+    err = np.abs(g[idx] - fd[idx]).max() / np.abs(g[idx]).max()
+    assert err < 1e-7, err
+
+
+def test_mlp_injection_labels_are_exact_for_quartics():
+    """On a fine field that is a quartic in x, the coarse 5-point linear
+    interpolation reproduces every label: the fine node 2j+1 sits on the
+    coarse face j+1/2 (cell-centred nodes)."""
+    M = _mlp()
+    p = M.init(10, last_scale=0.0)
+    n = 40
+    xf = (np.arange(2 * n) + 0.5) / (2 * n)
+    f = 1 + 2 * xf - 3 * xf ** 2 + 0.5 * xf ** 3 + 4 * xf ** 4
+    X, T = M.samples_from_fine(f)
+    assert len(T) == (n - 4) + (n - 4)
+    assert M.loss(p, X, T) < 1e-24
+
+
+def test_mlp_adam_first_step():
+    M = _mlp()
+    p = np.linspace(-1, 1, M.NPARAM)
+    g = np.linspace(2, -3, M.NPARAM) + 0.01
+    z = np.zeros(M.NPARAM)
+    p1, m, v = M.adam(p, g, z, z, 1, lr=1e-3, eps=1e-12)
+    assert np.allclose(p1, p - 1e-3 * np.sign(g), rtol=0, atol=1e-9)  # eps / |g| <= 1e-6 here
+
+
+@pytest.mark.parametrize("x,want", [(1 + 2 ** -8, 1.0), (1 + 3 * 2 ** -9, 1 + 2 ** -7), (1 + 2 ** -8 + 2 ** -20, 1 + 2 ** -7),
+                                    (-(1 + 2 ** -7 + 2 ** -8), -(1 + 2 ** -6)), (3.0, 3.0), (0.0, 0.0),
+                                    (1 + 2 ** -8 + 2 ** -30, 1.0)])
+def test_bf16_rounding(orc, x, want):
+    # the last case: rounds to float first (1 + 2^-8 exactly), then ties to even
+    assert orc.bf16(x) == want
+
+
+def test_mlp_linear_weights_fifth_order_in_the_solver(orc):
+    """The solver with learned weights whose last layer is zero runs the
+    fifth-order linear interpolation on both sides of every face: on the smooth
+    2D advection of Sec. 5.2 the error of alpha_1 falls by 2^5 per refinement
+    (a mirrored right-biased stencil or a wrong candidate would break this)."""
+    from paper_2208_04488_amd import inputs as I
+    p = _mlp().init(5, last_scale=0.0)
+    err = []
+    for n in (16, 32):
+        pr = I.advection_2d(n)
+        o = orc.from_problem(pr, mlp=p)
+        W, t, _ = o.run(pr.W, cfl=pr.cfl, t_end=pr.t_end, dt_fixed=pr.dt_fixed)
+        c = -1.0 + (np.arange(n) + 0.5) * pr.dx[0]
+        Y, X = np.meshgrid(c, c, indexing="ij")
+        ex = 0.5 + 0.25 * np.sin(np.pi * (X + Y - 20.0 * t))
+        err.append(np.abs(W[pr.N + pr.D + 1, 0] - ex).mean())
+    order = np.log2(err[0] / err[1])
+    assert 4.7 < order < 5.3, (err, order)

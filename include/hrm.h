@@ -49,6 +49,7 @@ extern "C" {
 
 /* nonlinear weights of the interpolation */
 #define HRM_WEIGHTS_IS 0  /* incremental-stencil WENO weights (App. C) */
+#define HRM_WEIGHTS_MLP 1 /* learned weights (not in the paper; see hrm_set_mlp); FP64, dim <= 2 */
 
 /* grid flags */
 #define HRM_NO_LIMITERS 1   /* skip the interpolation and flux limiters (Sec. 4.3.2) */
@@ -153,6 +154,74 @@ int hrm_rk_stage(hrm_ctx* ctx, int stage, const double* d_Wn, const double* d_Ws
  * volume-fraction components change.  Cells with rho(e - qbar) <= 0 are left
  * unchanged and counted in hrm_diag.relax_bad. */
 int hrm_relax(hrm_ctx* ctx, double* d_W, void* stream);
+
+/* Learned interpolation weights (an extension; the paper's weights are those
+ * of App. C).  On a grid created with weights = HRM_WEIGHTS_MLP every
+ * characteristic variable is interpolated at i+1/2 (and mirrored for the
+ * right-biased value) as sum_k omega_k S_k over the three 3-point candidates
+ * of the fifth-order interpolation from u_{i-2..i+2},
+ *   S_l = (3u_{i-2} - 10u_{i-1} + 15u_i)/8, S_c = (-u_{i-1} + 6u_i + 3u_{i+1})/8,
+ *   S_r = (3u_i + 6u_{i+1} - u_{i+2})/8,
+ * omega_k proportional to d_k e^{tanh z_k} / (1e-6 + beta_k)^2, d = (1/16,
+ * 10/16, 5/16): the classical fifth-order WENO weights (Jiang & Shu
+ * smoothness indicators beta_k) of the normalised stencil
+ * x_j = (u_j - u_i) / max_j |u_j - u_i|, each rescaled by at most e either
+ * way by z = MLP(x), a 5-32-32-3 ReLU perceptron evaluated on the bfloat16
+ * matrix cores with float accumulation.  Where a weight is not finite the
+ * App. C value is used.  The limiters, HLLC, HCS and relaxation are
+ * unchanged.
+ * h_params: HOST array of 1347 floats, W1[5][32], b1[32], W2[32][32], b2[32],
+ * W3[32][3], b3[3] (rows = input unit); copied (synchronises the context's
+ * last stream).  Required before any operator call on such a grid. */
+int hrm_set_mlp(hrm_ctx* ctx, const float* h_params);
+
+/* The learned interpolation alone, for checking it: n stencils d_U5[i][0..4]
+ * (DEVICE, doubles, u_{i-2..i+2}) -> d_val[i] (DEVICE doubles) and the
+ * weights d_omega[i][0..2] (DEVICE floats), exactly as the solver evaluates
+ * them.  Needs a grid with HRM_WEIGHTS_MLP after hrm_set_mlp. */
+int hrm_mlp_infer(hrm_ctx* ctx, const double* d_U5, long long n, double* d_val, float* d_omega, void* stream);
+
+/* ---- Training of the learned weights (context-free; float32 on the GPU) ----
+ * Pairs come from a fine 1D ensemble (layout as hrm_batch_*, problem b owning
+ * fine cells h_offsets[b] .. h_offsets[b+1]-1 of d_W, M = 2N+1 components)
+ * by injection: coarse node j = fine node 2j, and the label of the coarse
+ * face j+1/2 is fine node 2j+1 (cell-centred nodes).  For every problem with
+ * an even fine length 2n, n >= 5, and every field of the primitive vector
+ * (alpha_k rho_k, u, p, alpha_k; App. D), in that order: the left-biased
+ * stencils (coarse j-2..j+2) for j = 2..n-3, then the mirrored right-biased
+ * ones (coarse j+3..j-1) for j = 1..n-4.  A pair is stored normalised,
+ *   x_j = (u_j - u_i) r, r = 1 / s, s = max_j |u_j - u_i|,
+ *   t = (label - u_i) r,
+ * with r = 0 (x = 0, t = 0: no contribution to the loss) where
+ * s <= 1e-10 max_j |u_j| (variations at round-off level carry no shape) or
+ * |t| > 4 (a feature the coarse stencil does not see: beyond every convex
+ * combination of the candidates, whose values lie within [-3.5, 3.5]);
+ * as d_X[s][0..7] = (x_0..x_4, 0, 0, 0) and d_T[s] (DEVICE floats).
+ * With d_X = d_T = NULL only *nsamples is set (size query).  Otherwise
+ * capacity (in samples) must hold them all.  Synchronises `stream`. */
+int hrm_mlp_extract(const hrm_eos* eos, const double* d_W, long long T, int nprob, const long long* h_offsets,
+                    float* d_X, float* d_T, long long capacity, long long* nsamples, void* stream);
+
+/* Floats of workspace hrm_mlp_grad needs for a minibatch of `count`. */
+long long hrm_mlp_grad_workspace(int count);
+
+/* Mean squared residual over a minibatch and its gradient (float32):
+ *   L = (1/count) sum_s (sum_k omega_k(x_s) S_k(x_s) - t_s)^2,
+ * omega as in hrm_set_mlp (in float, without bfloat16 rounding), over the
+ * samples (first + s * stride) mod nsamp, s < count, of d_X, d_T.
+ * d_params: 1347 floats (layout of hrm_set_mlp, DEVICE); writes d_grad[1347]
+ * and d_loss[1] (DEVICE).  Per-workgroup partial sums go to d_work (at least
+ * hrm_mlp_grad_workspace(count) floats) and are reduced in a fixed order, so
+ * the result is deterministic. */
+int hrm_mlp_grad(const float* d_params, const float* d_X, const float* d_T, long long nsamp, long long first,
+                 long long stride, int count, float* d_grad, float* d_loss, float* d_work, long long work_floats,
+                 void* stream);
+
+/* Adam step `step` (>= 1) on the 1347 parameters, all DEVICE floats:
+ *   m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ *   p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps). */
+int hrm_mlp_adam(float* d_params, const float* d_grad, float* d_m, float* d_v, int step, float lr, float beta1,
+                 float beta2, float eps, void* stream);
 
 /* One full SSP-RK3 step of the fractional algorithm on d_W in place:
  * wavespeed of W^n, time step into d_slot (see hrm_compute_dt), three stages

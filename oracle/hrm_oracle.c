@@ -244,11 +244,14 @@ static double hllc(const orc_setup *s, int n, const orc_state *L, const orc_stat
 /* candidates of the fifth-order interpolation from u_{i-2..i+2}:             */
 /*   S_l = (3u_{i-2} - 10u_{i-1} + 15u_i)/8,  S_c = (-u_{i-1} + 6u_i + 3u_{i+1})/8, */
 /*   S_r = (3u_i + 6u_{i+1} - u_{i+2})/8,                                      */
-/* whose linear weights d = (1/16, 10/16, 5/16) give the fifth-order value.   */
+/* whose linear weights d = (1/16, 10/16, 5/16) give the fifth-order value;  */
+/* the value is formed as S_c + omega_l (S_l - S_c) + omega_r (S_r - S_c).    */
 /* A perceptron 5-32-32-3 (ReLU) maps the normalised stencil                 */
-/*   x_j = (u_j - u_i) / max_j |u_j - u_i|      (x = 0 if the maximum is 0)    */
-/* to logits z, and omega = softmax(z + ln d): a zero last layer gives the    */
-/* linear weights.  Parameters, as 1347 numbers in this order: W1[5][32],     */
+/*   x_j = (u_j - u_i) r,  r = 1 / max_j |u_j - u_i|   (x = 0 if the max is 0) */
+/* to logits z that correct the classical WENO5 weights of x (Jiang & Shu):   */
+/*   omega_k = d_k e^{z_k} / (eps + beta_k)^2, normalised, eps = 1e-6;        */
+/* a zero last layer gives those classical weights.  Parameters, as 1347      */
+/* numbers in this order: W1[5][32],                                          */
 /* b1[32], W2[32][32], b2[32], W3[32][3], b3[3] (row = input unit).           */
 /* The number formats are those of a bfloat16 matrix-core evaluation with     */
 /* float accumulation: inputs, W1, b1, W2, W3 and both hidden activations     */
@@ -272,6 +275,20 @@ static double bf16_round(double x)
 
 static double to_float(double x) { return (double)(float)x; }
 
+#define MLP_EPS 1e-6
+#define MLP_BOUND 1.0 /* each classical weight is rescaled by at most e^{+-1} */
+
+/* smoothness indicators of the three candidates (Jiang & Shu) */
+static void weno5_beta(const double *x, double *beta)
+{
+    const double a0 = x[0] - 2.0 * x[1] + x[2], b0 = x[0] - 4.0 * x[1] + 3.0 * x[2];
+    const double a1 = x[1] - 2.0 * x[2] + x[3], b1 = x[1] - x[3];
+    const double a2 = x[2] - 2.0 * x[3] + x[4], b2 = 3.0 * x[2] - 4.0 * x[3] + x[4];
+    beta[0] = 13.0 / 12.0 * a0 * a0 + 0.25 * b0 * b0;
+    beta[1] = 13.0 / 12.0 * a1 * a1 + 0.25 * b1 * b1;
+    beta[2] = 13.0 / 12.0 * a2 * a2 + 0.25 * b2 * b2;
+}
+
 /* omega[3] for the normalised stencil x[5] */
 static void mlp_weights(const double *P, const double *x, double *omega)
 {
@@ -293,15 +310,23 @@ static void mlp_weights(const double *P, const double *x, double *omega)
         for (int h = 0; h < 32; ++h) a += h2[h] * bf16_round(W3[h * 3 + k]);
         z[k] = a;
     }
-    const double lnd[3] = {log(1.0 / 16.0), log(10.0 / 16.0), log(5.0 / 16.0)};
-    double m = z[0] + lnd[0];
-    for (int k = 1; k < 3; ++k) m = fmax(m, z[k] + lnd[k]);
-    double e[3], sum = 0.0;
+    /* prior: the classical fifth-order WENO weights d_k / (eps + beta_k)^2 of
+     * the normalised stencil (taken as float, as the device holds it) */
+    double xf[5];
+    for (int j = 0; j < 5; ++j) xf[j] = to_float(x[j]);
+    double beta[3];
+    weno5_beta(xf, beta);
+    const double d[3] = {1.0 / 16.0, 10.0 / 16.0, 5.0 / 16.0};
+    double zc[3];
+    for (int k = 0; k < 3; ++k) zc[k] = MLP_BOUND * tanh(z[k]);
+    double m = fmax(zc[0], fmax(zc[1], zc[2]));
+    double a[3], sum = 0.0;
     for (int k = 0; k < 3; ++k) {
-        e[k] = exp(z[k] + lnd[k] - m);
-        sum += e[k];
+        const double eb = MLP_EPS + beta[k];
+        a[k] = d[k] * exp(zc[k] - m) / (eb * eb);
+        sum += a[k];
     }
-    for (int k = 0; k < 3; ++k) omega[k] = e[k] / sum;
+    for (int k = 0; k < 3; ++k) omega[k] = a[k] / sum;
 }
 
 /* learned interpolation of u = (u_{i-2}..u_{i+2}); returns 0 (and leaves
@@ -310,15 +335,18 @@ static int mlp_interp(const double *P, const double *u, double *out, double *ome
 {
     double s = 0.0;
     for (int j = 0; j < 5; ++j) s = fmax(s, fabs(u[j] - u[2]));
+    const double r = s > 0.0 ? 1.0 / s : 0.0;
     double x[5];
-    for (int j = 0; j < 5; ++j) x[j] = s > 0.0 ? (u[j] - u[2]) / s : 0.0;
+    for (int j = 0; j < 5; ++j) x[j] = (u[j] - u[2]) * r;
     mlp_weights(P, x, omega);
     for (int k = 0; k < 3; ++k)
         if (!isfinite(omega[k])) return 0;
     const double sl = (3.0 * u[0] - 10.0 * u[1] + 15.0 * u[2]) / 8.0;
     const double sc = (-u[1] + 6.0 * u[2] + 3.0 * u[3]) / 8.0;
     const double sr = (3.0 * u[2] + 6.0 * u[3] - u[4]) / 8.0;
-    *out = omega[0] * sl + omega[1] * sc + omega[2] * sr;
+    /* sum_k omega_k S_k with the weights summing to one, written so that a
+     * constant stencil is reproduced exactly */
+    *out = sc + omega[0] * (sl - sc) + omega[2] * (sr - sc);
     return 1;
 }
 

@@ -12,8 +12,11 @@ from u_{i-2..i+2}:
     S_c = (-u_{i-1} + 6u_i + 3u_{i+1})/8
     S_r = (3u_i + 6u_{i+1} - u_{i+2})/8,     linear weights d = (1/16, 10/16, 5/16)
 
-with omega = softmax(z + ln d) and z = MLP(x), a 5-32-32-3 perceptron with
-ReLU on the normalised stencil x_j = (u_j - u_i) / max_j |u_j - u_i|.
+with omega_k proportional to d_k e^{z_k} / (eps + beta_k)^2: the network's
+logits z correct the classical WENO5 weights (Jiang & Shu smoothness
+indicators beta_k of x, eps = 1e-6), and z = MLP(x) comes from a 5-32-32-3
+perceptron with ReLU on the normalised stencil x_j = (u_j - u_i) r,
+r = 1 / max_j |u_j - u_i|.
 
 Training pairs come from a fine solution by injection: the coarse stencil is
 every other fine node, and the label is the fine node at the coarse face
@@ -56,7 +59,7 @@ def pack(d) -> np.ndarray:
 
 def init(seed: int, last_scale: float = 0.0) -> np.ndarray:
     """He-uniform hidden layers, zero biases; the last layer scaled by
-    `last_scale` (0: the initial network gives exactly the linear weights)."""
+    `last_scale` (0: the initial network gives the classical WENO5 weights)."""
     rng = np.random.default_rng(seed)
     d = {"W1": rng.uniform(-1, 1, (5, 32)) * np.sqrt(6.0 / 5.0), "b1": np.zeros(32),
          "W2": rng.uniform(-1, 1, (32, 32)) * np.sqrt(6.0 / 32.0), "b2": np.zeros(32),
@@ -65,12 +68,29 @@ def init(seed: int, last_scale: float = 0.0) -> np.ndarray:
 
 
 def normalise(u5):
-    """x = (u - u_i) / s, s = max |u - u_i| per row (x = 0 where s = 0)."""
+    """x = (u - u_i) r with r = 1 / s, s = max |u - u_i| per row (x = 0 where s = 0)."""
     u5 = np.asarray(u5, dtype=np.float64)
     du = u5 - u5[..., 2:3]
     s = np.abs(du).max(axis=-1, keepdims=True)
-    x = np.divide(du, s, out=np.zeros_like(du), where=s > 0)
-    return x, s[..., 0]
+    r = np.divide(1.0, s, out=np.zeros_like(s), where=s > 0)
+    return du * r, s[..., 0]
+
+
+EPS = 1e-6
+BOUND = 1.0   # the network rescales each classical weight by at most e^{+-BOUND}
+
+
+def beta(X):
+    """Smoothness indicators of the three candidates (Jiang & Shu) of X (n, 5)."""
+    x0, x1, x2, x3, x4 = (X[:, j] for j in range(5))
+    return np.stack([13 / 12 * (x0 - 2 * x1 + x2) ** 2 + 0.25 * (x0 - 4 * x1 + 3 * x2) ** 2,
+                     13 / 12 * (x1 - 2 * x2 + x3) ** 2 + 0.25 * (x1 - x3) ** 2,
+                     13 / 12 * (x2 - 2 * x3 + x4) ** 2 + 0.25 * (3 * x2 - 4 * x3 + x4) ** 2], axis=1)
+
+
+def prior(X):
+    """ln of the classical WENO5 weights' numerators d_k / (eps + beta_k)^2."""
+    return np.log(LIN) - 2.0 * np.log(EPS + beta(X))
 
 
 def forward(p, X):
@@ -81,7 +101,8 @@ def forward(p, X):
     a2 = h1 @ q["W2"] + q["b2"]
     h2 = np.maximum(a2, 0.0)
     z = h2 @ q["W3"] + q["b3"]
-    y = z + np.log(LIN)
+    zc = BOUND * np.tanh(z)
+    y = zc + prior(X)
     y = y - y.max(axis=1, keepdims=True)
     e = np.exp(y)
     w = e / e.sum(axis=1, keepdims=True)
@@ -117,7 +138,8 @@ def grad(p, X, T):
     yhat = (w * S).sum(axis=1)
     dy = 2.0 * (yhat - T) / n            # d loss / d yhat
     dw = dy[:, None] * S                 # d loss / d w_k
-    dz = w * (dw - (w * dw).sum(axis=1, keepdims=True))   # softmax Jacobian
+    dzc = w * (dw - (w * dw).sum(axis=1, keepdims=True))  # softmax Jacobian
+    dz = dzc * BOUND * (1.0 - np.tanh(f["z"]) ** 2)
     g = {"W3": f["h2"].T @ dz, "b3": dz.sum(axis=0)}
     dh2 = dz @ q["W3"].T * (f["a2"] > 0)
     g["W2"] = f["h1"].T @ dh2
@@ -149,13 +171,15 @@ def adam(p, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def samples_from_fine(f):
+def samples_from_fine(f, keep_degenerate=False):
     """Training pairs from one fine field f (2n nodes, transmissive problem):
     for every coarse face j+1/2 with the whole coarse stencil j-2..j+2 inside,
     the stencil (f[2(j-2)], ..., f[2(j+2)]) and the label f[2j+1]; both
     orientations (the mirrored stencil f[2(j+3)], ..., f[2(j-1)] interpolates
-    to the same face from the right).  Returns (X, T) in normalised units,
-    dropping stencils with s = 0."""
+    to the same face from the right), all left-biased pairs first.  Returns
+    (X, T) in normalised units; stencils with s <= 1e-10 max |u_j| or a label
+    beyond |t| = 4 (x = 0, t = 0: they add nothing to the loss or its
+    gradient) are dropped unless keep_degenerate."""
     f = np.asarray(f, dtype=np.float64)
     c = f[0::2]
     n = c.size
@@ -171,7 +195,17 @@ def samples_from_fine(f):
     if not X:
         return np.zeros((0, 5)), np.zeros(0)
     U = np.array(X)
-    x, s = normalise(U)
-    t = np.divide(np.array(T) - U[:, 2], s, out=np.zeros(len(T)), where=s > 0)
-    keep = s > 0
-    return x[keep], t[keep]
+    du = U - U[:, 2:3]
+    s = np.abs(du).max(axis=1)
+    # variations at round-off level carry no shape, and labels beyond [-4, 4]
+    # in normalised units cannot be reached by any convex combination of the
+    # candidates (|S_k| <= 3.5): such pairs are neutral
+    live = s > 1e-10 * np.abs(U).max(axis=1)
+    r = np.divide(1.0, s, out=np.zeros_like(s), where=live)
+    live &= np.abs((np.array(T) - U[:, 2]) * r) <= 4.0
+    r = np.where(live, r, 0.0)
+    x = du * r[:, None]
+    t = (np.array(T) - U[:, 2]) * r
+    if keep_degenerate:
+        return x, t
+    return x[live], t[live]

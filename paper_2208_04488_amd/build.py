@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhrm.so")
-SOURCES = ["hrm.hip", "hrm_batch.hip"]
+SOURCES = ["hrm.hip", "hrm_batch.hip", "hrm_mlp.hip"]
 # per-source flags: the persistent batch kernel wraps the face arithmetic in
 # problem / step / stage / tile loops; machine-level loop-invariant code motion
 # would lift dozens of FP64 constant materialisations out of them and keep

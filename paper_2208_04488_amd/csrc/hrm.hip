@@ -49,7 +49,7 @@ constexpr int MODE_WRITE = 0, MODE_ADD = 1, MODE_FINAL = 2;
 // across it.  DIR == 0: blockDim = (BS, BA), across = y, blockIdx.z = z.
 // DIR == 1: blockDim = (BA, BS), across = x, blockIdx.z = z.
 // DIR == 2: blockDim = (BA, BS), across = x, blockIdx.y = y.
-template <int N, int D, int DIR, int BS, int BA, typename R>
+template <int N, int D, int DIR, int BS, int BA, typename R, int WT>
 __global__ void __launch_bounds__(BS* BA, 2) k_sweep(const SweepArgs A)
 {
     using F = NodeFields<N, D>;
@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(BS* BA, 2) k_sweep(const SweepArgs A)
     double G[M], Gp[NA];
     {
         unsigned lc[C_N] = {0, 0, 0, 0, 0, 0, 0};
-        face_flux<N, D, DIR, NS, FS, R>(lds + base(ta, ts), A.e, A.P, A.slot[1 + DIR], G, Gp, lc);
+        face_flux<N, D, DIR, NS, FS, R, WT>(lds + base(ta, ts), A.e, A.P, A.slot[1 + DIR], G, Gp, lc);
         // face c0+ts is counted once: the last face of a tile is the first
         // face of the next tile unless it is the boundary face nsw
         const int f = c0 + ts;
@@ -273,6 +273,27 @@ __global__ void __launch_bounds__(256) k_reduce_dt(const double* part, int nb, d
     }
 }
 
+// learned interpolation of n stencils U[i][0..4] (one lane per stencil; the
+// whole wave evaluates the network together)
+__global__ void __launch_bounds__(64) k_mlp_infer(const MlpPacked* m, const double* U, long long n, double eps,
+                                                  double* val, float* om)
+{
+    const long long i = (long long)blockIdx.x * 64 + threadIdx.x;
+    double u[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (i < n)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) u[j] = U[i * 5 + j];
+    float x[5], z[3], w[3];
+    mlp_inputs<double>(u, x);
+    mlp_logits(m, x, z);
+    const bool ok = mlp_omega(z, x, w);
+    if (i < n) {
+        val[i] = ok ? mlp_value<double>(u, w) : weno_is<double>(u[0], u[1], u[2], u[3], u[4], eps);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) om[i * 3 + k] = w[k];
+    }
+}
+
 __global__ void k_zero_u64(unsigned long long* p, int n)
 {
     if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
@@ -297,6 +318,8 @@ struct hrm_ctx {
     int npart;
     double* d_maxs;
     unsigned long long* d_cnt;
+    hrm::MlpPacked* d_mlp;  // learned weights (HRM_WEIGHTS_MLP)
+    int mlp_ready;
     hipStream_t last_stream;
     // hrm_step replay: one captured RK3 step per argument set
     hipStream_t cap_stream;
@@ -391,10 +414,17 @@ struct Ops {
         A.bchi = c->bchi[DIR];
         A.idx = 1.0 / c->dx[DIR];
         TimerScope t(c, HRM_T_SWEEP_X + DIR, s);
+        if constexpr (D <= 2) {
+            // learned weights: FP64 face arithmetic, one and two dimensions
+            if (c->weights == HRM_WEIGHTS_MLP) {
+                hipLaunchKernelGGL((hrm::k_sweep<N, D, DIR, BS, BA, double, 1>), grd, blk, 0, s, A);
+                return;
+            }
+        }
         if (c->precision == HRM_FP32)
-            hipLaunchKernelGGL((hrm::k_sweep<N, D, DIR, BS, BA, float>), grd, blk, 0, s, A);
+            hipLaunchKernelGGL((hrm::k_sweep<N, D, DIR, BS, BA, float, 0>), grd, blk, 0, s, A);
         else
-            hipLaunchKernelGGL((hrm::k_sweep<N, D, DIR, BS, BA, double>), grd, blk, 0, s, A);
+            hipLaunchKernelGGL((hrm::k_sweep<N, D, DIR, BS, BA, double, 0>), grd, blk, 0, s, A);
     }
 
     static void sweep(hrm_ctx* c, int dir, hrm::SweepArgs& A, hipStream_t s)
@@ -461,6 +491,8 @@ hrm::SweepArgs base_args(hrm_ctx* c)
 int run_operator(hrm_ctx* c, const double* Ws, const double* Wn, double* Wout, double* rhs, const double* slot,
                  bool stage, double a, double b, int relax, hipStream_t s)
 {
+    if (c->weights == HRM_WEIGHTS_MLP && !c->mlp_ready)
+        return fail(c, HRM_EINVAL, "learned weights selected but hrm_set_mlp not called%s");
     hrm::SweepArgs A = base_args(c);
     A.Ws = Ws;
     A.Wn = Wn;
@@ -563,7 +595,8 @@ int hrm_create(const hrm_grid* g, const hrm_eos* e, const hrm_params* prm, hrm_c
         if (k > 0 && e->pinf[k] != 0.0) return HRM_EINVAL;  // one stiffened gas, species 0 (Sec. 4.2)
     }
     if (g->precision != HRM_FP64 && g->precision != HRM_FP32) return HRM_EINVAL;
-    if (g->weights != HRM_WEIGHTS_IS) return HRM_EUNSUPPORTED;
+    if (g->weights != HRM_WEIGHTS_IS && g->weights != HRM_WEIGHTS_MLP) return HRM_EINVAL;
+    if (g->weights == HRM_WEIGHTS_MLP && (g->precision != HRM_FP64 || g->dim > 2)) return HRM_EUNSUPPORTED;
 
     hrm_ctx* c = new (std::nothrow) hrm_ctx;
     if (!c) return HRM_ENOMEM;
@@ -631,6 +664,8 @@ int hrm_create(const hrm_grid* g, const hrm_eos* e, const hrm_params* prm, hrm_c
     ok = ok && hipMalloc((void**)&c->d_part, sizeof(double) * 3 * (size_t)c->npart) == hipSuccess;
     ok = ok && hipMalloc((void**)&c->d_maxs, sizeof(double) * 4) == hipSuccess;
     ok = ok && hipMalloc((void**)&c->d_cnt, sizeof(unsigned long long) * 8) == hipSuccess;
+    if (c->weights == HRM_WEIGHTS_MLP) ok = ok && hipMalloc((void**)&c->d_mlp, sizeof(hrm::MlpPacked)) == hipSuccess;
+    P.mlp = c->d_mlp;
     if (ok) ok = hipMemset(c->d_cnt, 0, sizeof(unsigned long long) * 8) == hipSuccess;
     if (ok) ok = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
@@ -657,6 +692,7 @@ int hrm_destroy(hrm_ctx* c)
     (void)hipFree(c->d_part);
     (void)hipFree(c->d_maxs);
     (void)hipFree(c->d_cnt);
+    (void)hipFree(c->d_mlp);
     drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
@@ -720,6 +756,36 @@ int hrm_relax(hrm_ctx* c, double* d_W, void* stream)
     c->last_stream = s;
     const int rc = dispatch(c, [&](auto ops) { decltype(ops)::relax(c, d_W, s); });
     return rc != HRM_OK ? rc : check_launch(c, "hrm_relax");
+}
+
+int hrm_set_mlp(hrm_ctx* c, const float* h_params)
+{
+    if (!c) return HRM_EINVAL;
+    if (c->weights != HRM_WEIGHTS_MLP) return fail(c, HRM_EINVAL, "hrm_set_mlp: the grid uses App. C weights%s");
+    if (!h_params) return fail(c, HRM_EINVAL, "hrm_set_mlp: NULL parameters%s");
+    hrm::MlpPacked pk;
+    hrm::mlp_pack_host(h_params, &pk);
+    // ordered after the work already enqueued by this context
+    if (hipStreamSynchronize(c->last_stream) != hipSuccess ||
+        hipMemcpy(c->d_mlp, &pk, sizeof(pk), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(c, HRM_EDEVICE, "hrm_set_mlp: copy failed%s");
+    c->mlp_ready = 1;
+    return HRM_OK;
+}
+
+int hrm_mlp_infer(hrm_ctx* c, const double* d_U5, long long n, double* d_val, float* d_omega, void* stream)
+{
+    if (!c) return HRM_EINVAL;
+    if (c->weights != HRM_WEIGHTS_MLP || !c->mlp_ready)
+        return fail(c, HRM_EINVAL, "hrm_mlp_infer: no learned weights on this grid%s");
+    if (n < 0 || (n > 0 && (!valid_ptr(d_U5) || !valid_ptr(d_val) || !d_omega)))
+        return fail(c, HRM_EINVAL, "hrm_mlp_infer: bad arguments%s");
+    if (n == 0) return HRM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    hipLaunchKernelGGL(hrm::k_mlp_infer, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, c->d_mlp, d_U5, n,
+                       c->par.eps_weno, d_val, d_omega);
+    return check_launch(c, "hrm_mlp_infer");
 }
 
 int hrm_step(hrm_ctx* c, double* d_W, double cfl, double dt_fixed, double t_end, double* d_slot, void* stream)

@@ -31,6 +31,8 @@ struct EosDev {
     double cp[MAXN];    // gamma_k c_v,k
 };
 
+struct MlpPacked;  // learned interpolation weights (hrm_mlp.hpp)
+
 struct ParDev {
     double eps_weno;
     double eps_i_ar, eps_i_a, hs_i_ar, hs_i_a, hs_i_rc2;
@@ -39,6 +41,7 @@ struct ParDev {
     double hcs_a, hcs_b, hcs_c;  // eq:reconstructed_G coefficients from psi
     int flags;
     int fast_flux_limiter;  // eps_f >= eps_f^HS for all three quantities
+    const MlpPacked* mlp;   // packed network of the learned weights (device), or null
 };
 
 // counters accumulated per thread, flushed once per wave

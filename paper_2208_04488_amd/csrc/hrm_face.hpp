@@ -4,6 +4,7 @@
 #pragma once
 
 #include "hrm_device.hpp"
+#include "hrm_mlp.hpp"
 
 namespace hrm {
 
@@ -59,6 +60,28 @@ __device__ inline void weno_pair(const R* v, double eps, R& l, R& r)
     r = weno_is<R>(v[5], v[4], v[3], v[2], v[1], eps);
 }
 
+// the pair of interpolated values at i+1/2 from v[0..5] = nodes i-2..i+3:
+// App. C weights (WT = 0), or the learned weights (WT = 1) with App. C as the
+// fallback where a learned weight is not finite.  WT = 1 must be reached by
+// every lane of the wave (matrix-core evaluation).
+template <typename R, int WT>
+__device__ inline void interp_pair(const R* v, double eps, const MlpPacked* mlp, R& l, R& r)
+{
+    if constexpr (WT == 0) {
+        weno_pair<R>(v, eps, l, r);
+    } else {
+        const R ul[5] = {v[0], v[1], v[2], v[3], v[4]};
+        const R ur[5] = {v[5], v[4], v[3], v[2], v[1]};
+        float xl[5], xr[5], zl[3], zr[3], wl[3], wr[3];
+        mlp_inputs<R>(ul, xl);
+        mlp_inputs<R>(ur, xr);
+        mlp_logits(mlp, xl, zl);
+        mlp_logits(mlp, xr, zr);
+        l = mlp_omega(zl, xl, wl) ? mlp_value<R>(ul, wl) : weno_is<R>(v[0], v[1], v[2], v[3], v[4], eps);
+        r = mlp_omega(zr, xr, wr) ? mlp_value<R>(ur, wr) : weno_is<R>(v[5], v[4], v[3], v[2], v[1], eps);
+    }
+}
+
 // normalised fourth-order second derivative of the shock sensor (Sec. 4.3.1)
 template <typename R>
 __device__ inline R sensor_ratio_t(R v0, R v1, R v2, R v3, R v4)
@@ -71,7 +94,7 @@ __device__ inline R sensor_ratio_t(R v0, R v1, R v2, R v3, R v4)
 // Output: G = G^{**,-}_{i+1/2} (M slots) and Gp = alpha slots of G^{**,+}.
 // R is the face arithmetic type; node data, the flux limiter and the outputs
 // are double.
-template <int N, int D, int DIR, int NS, int FS, typename R>
+template <int N, int D, int DIR, int NS, int FS, typename R, int WT = 0>
 __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, double lam, double* G, double* Gp,
                           unsigned* cnt)
 {
@@ -124,13 +147,13 @@ __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, do
     R UL[M], UR[M], v[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) v[j] = dv(j, F::U + DIR) - dv(j, F::P) * irc;
-    weno_pair<R>(v, eps, UL[0], UR[0]);
+    interp_pair<R, WT>(v, eps, P.mlp, UL[0], UR[0]);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         const R s = arb[k] * irc2;
 #pragma unroll
         for (int j = 0; j < 6; ++j) v[j] = dv(j, k) - s * dv(j, F::P);
-        weno_pair<R>(v, eps, UL[1 + k], UR[1 + k]);
+        interp_pair<R, WT>(v, eps, P.mlp, UL[1 + k], UR[1 + k]);
     }
     {
         int t = 0;
@@ -139,7 +162,7 @@ __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, do
             if (d == DIR) continue;
 #pragma unroll
             for (int j = 0; j < 6; ++j) v[j] = dv(j, F::U + d);
-            weno_pair<R>(v, eps, UL[1 + N + t], UR[1 + N + t]);
+            interp_pair<R, WT>(v, eps, P.mlp, UL[1 + N + t], UR[1 + N + t]);
             ++t;
         }
     }
@@ -147,11 +170,11 @@ __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, do
     for (int k = 0; k < N - 1; ++k) {
 #pragma unroll
         for (int j = 0; j < 6; ++j) v[j] = dv(j, IA + k);
-        weno_pair<R>(v, eps, UL[N + D + k], UR[N + D + k]);
+        interp_pair<R, WT>(v, eps, P.mlp, UL[N + D + k], UR[N + D + k]);
     }
 #pragma unroll
     for (int j = 0; j < 6; ++j) v[j] = dv(j, F::U + DIR) + dv(j, F::P) * irc;
-    weno_pair<R>(v, eps, UL[M - 1], UR[M - 1]);
+    interp_pair<R, WT>(v, eps, P.mlp, UL[M - 1], UR[M - 1]);
 
     // back to primitive slots: V = R U
     St<N, D, R> VL, VR;

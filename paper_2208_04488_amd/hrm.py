@@ -22,7 +22,8 @@ MAX_SPECIES = 8
 HRM_OK, HRM_EINVAL, HRM_ENOMEM, HRM_EDEVICE, HRM_EADMISSIBLE, HRM_EUNSUPPORTED = range(6)
 BC_TRANSMISSIVE, BC_PERIODIC = 0, 1
 FP64, FP32 = 0, 1
-WEIGHTS_IS = 0
+WEIGHTS_IS, WEIGHTS_MLP = 0, 1
+MLP_NPARAM = 1347
 NO_LIMITERS, NO_BLEND, FIRST_ORDER, FUSE_RELAX, NO_GRAPH = 1, 2, 4, 8, 16
 
 
@@ -91,6 +92,17 @@ def _load():
     L.hrm_batch_run.argtypes = [vp, vp, ctypes.c_int, dp, vp]
     L.hrm_batch_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.hrm_batch_get_diagnostics.argtypes = [vp, ctypes.POINTER(hrm_diag)]
+    fp = ctypes.POINTER(ctypes.c_float)
+    ll = ctypes.c_longlong
+    L.hrm_set_mlp.argtypes = [vp, fp]
+    L.hrm_mlp_infer.argtypes = [vp, vp, ll, vp, vp, vp]
+    L.hrm_mlp_extract.argtypes = [ctypes.POINTER(hrm_eos), vp, ll, ctypes.c_int, ctypes.POINTER(ll), vp, vp, ll,
+                                  ctypes.POINTER(ll), vp]
+    L.hrm_mlp_grad_workspace.argtypes = [ctypes.c_int]
+    L.hrm_mlp_grad_workspace.restype = ll
+    L.hrm_mlp_grad.argtypes = [vp, vp, vp, ll, ll, ll, ctypes.c_int, vp, vp, vp, ll, vp]
+    L.hrm_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                               ctypes.c_float, vp]
     return L
 
 
@@ -100,7 +112,7 @@ lib = _load()
 def header_functions(path: str = HEADER):
     """Names of the functions include/hrm.h declares."""
     txt = open(path).read()
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(hrm_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|void|long long|const char\*)\s+(hrm_\w+)\s*\(", txt, re.M)))
 
 
 def _check(ctx, rc):
@@ -118,6 +130,14 @@ def _ptr(t) -> int:
     import torch
     if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
         raise ValueError("device arrays must be contiguous float64 CUDA tensors")
+    return t.data_ptr()
+
+
+def _ptrf(t) -> int:
+    """Device pointer of a contiguous float32 CUDA tensor."""
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError("device arrays must be contiguous float32 CUDA tensors")
     return t.data_ptr()
 
 
@@ -205,6 +225,51 @@ def hrm_get_timing(ctx) -> dict:
     return {k: (ms[i], cnt[i]) for i, k in enumerate(TIMERS)}
 
 
+def hrm_set_mlp(ctx, params):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    if p.size != MLP_NPARAM:
+        raise ValueError(f"the network has {MLP_NPARAM} parameters")
+    return _check(ctx, lib.hrm_set_mlp(ctx, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+
+def hrm_mlp_infer(ctx, U5, val, omega, stream=None):
+    n = U5.shape[0]
+    return _check(ctx, lib.hrm_mlp_infer(ctx, _ptr(U5), n, _ptr(val), _ptrf(omega), _stream(stream)))
+
+
+def hrm_mlp_extract(eos: hrm_eos, W, offsets, X=None, T=None, stream=None) -> int:
+    """Training pairs of a fine ensemble; returns their number (size query
+    when X and T are None)."""
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    n = ctypes.c_longlong()
+    cap = 0 if X is None else X.shape[0]
+    rc = lib.hrm_mlp_extract(ctypes.byref(eos), 0 if W is None else _ptr(W), int(off[-1]), len(off) - 1,
+                             off.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)),
+                             0 if X is None else _ptrf(X), 0 if T is None else _ptrf(T), cap, ctypes.byref(n),
+                             _stream(stream) if X is not None else 0)
+    if rc != HRM_OK:
+        raise HrmError(rc, "hrm_mlp_extract rejected its arguments")
+    return n.value
+
+
+def hrm_mlp_grad_workspace(count) -> int:
+    return int(lib.hrm_mlp_grad_workspace(int(count)))
+
+
+def hrm_mlp_grad(params, X, T, first, stride, count, grad, loss, work, stream=None):
+    rc = lib.hrm_mlp_grad(_ptrf(params), _ptrf(X), _ptrf(T), X.shape[0], int(first), int(stride), int(count),
+                          _ptrf(grad), _ptrf(loss), _ptrf(work), work.numel(), _stream(stream))
+    if rc != HRM_OK:
+        raise HrmError(rc, "hrm_mlp_grad rejected its arguments")
+
+
+def hrm_mlp_adam(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    rc = lib.hrm_mlp_adam(_ptrf(params), _ptrf(grad), _ptrf(m), _ptrf(v), int(step), float(lr), float(beta1),
+                          float(beta2), float(eps), _stream(stream))
+    if rc != HRM_OK:
+        raise HrmError(rc, "hrm_mlp_adam rejected its arguments")
+
+
 def _bcheck(b, rc):
     if rc != HRM_OK:
         msg = lib.hrm_batch_last_error(b).decode() if b else ""
@@ -280,18 +345,22 @@ def make_eos(gamma, cv, pinf, q) -> hrm_eos:
 class Solver:
     """A context plus device state for one problem from ``inputs``."""
 
-    def __init__(self, prob, flags=FUSE_RELAX, precision=FP64, params: Optional[hrm_params] = None, W=None):
+    def __init__(self, prob, flags=FUSE_RELAX, precision=FP64, params: Optional[hrm_params] = None, W=None,
+                 mlp=None):
         import torch
         self.torch = torch
         self.prob = prob
         e = prob.eos
-        self.grid = make_grid(prob.D, prob.n, prob.dx, prob.bc, precision=precision, flags=flags)
+        self.grid = make_grid(prob.D, prob.n, prob.dx, prob.bc, precision=precision, flags=flags,
+                              weights=WEIGHTS_IS if mlp is None else WEIGHTS_MLP)
         self.eos = make_eos(e.gamma, e.cv, e.pinf, e.q)
         self.ctx = hrm_create(self.grid, self.eos, params)
         dev = torch.device("cuda")
         self.W = torch.from_numpy(np.ascontiguousarray(prob.W if W is None else W)).to(dev)
         self.slot = torch.zeros(8, dtype=torch.float64, device=dev)
         self.maxs = torch.zeros(4, dtype=torch.float64, device=dev)
+        if mlp is not None:
+            hrm_set_mlp(self.ctx, mlp)
 
     def close(self):
         if self.ctx:

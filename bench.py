@@ -125,6 +125,82 @@ def bench_batch(args):
     return out
 
 
+MLP_FLOPS_PER_STENCIL = 2 * (5 * 32 + 32 * 32 + 32 * 3)  # algorithmic multiply-adds x 2
+
+
+def bench_learned(args):
+    """Learned interpolation weights against the plain method on the planar
+    config-1 shock tube at 2048 x 1024 (FP64 state; the network in bfloat16
+    on the matrix cores).  The network is trained first, on the GPU, from a
+    fine ensemble of Riemann problems (untimed)."""
+    import numpy as np
+    import torch
+    from paper_2208_04488_amd import hrm, learned
+    from paper_2208_04488_amd import inputs as I
+
+    t0 = time.perf_counter()
+    fine = learned.fine_ensemble(nprob=1024, nmin=100, nmax=1000, seed=4001)
+    X, T = learned.training_data(fine, snapshots=(40, 120))
+    p0 = learned.init_params(0, last_scale=0.0)
+    loss0 = learned.mean_loss(p0, X, T)
+    params, _ = learned.train(X, T, steps=3000, count=16384, lr=2e-3, seed=0)
+    loss1 = learned.mean_loss(params, X, T)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    npairs = X.shape[0]
+    del X, T
+
+    prob = I.config5(args.learned_nx, args.learned_ny)
+    N, D, M = prob.N, prob.D, prob.M
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, mlp in (("plain", None), ("learned", params)):
+        s = hrm.Solver(prob, flags=hrm.FUSE_RELAX, mlp=mlp)
+        for _ in range(args.warmup):
+            s.step(cfl=prob.cfl)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.learned_steps):
+            s.step(cfl=prob.cfl)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        hrm.hrm_set_timing(s.ctx, (1 << 0) | (1 << 1))
+        hrm.hrm_get_timing(s.ctx)
+        for _ in range(5):
+            s.step(cfl=prob.cfl)
+        tm = hrm.hrm_get_timing(s.ctx)
+        hrm.hrm_set_timing(s.ctx, 0)
+        d = s.diagnostics()
+        res[name] = dict(ms=ms, W=s.state(), relax_bad=d["relax_bad"],
+                         sweep_ms={k: tm[k][0] / max(tm[k][1], 1) for k in ("sweep_x", "sweep_y")})
+        s.close()
+    nx, ny = prob.n[0], prob.n[1]
+    faces = (nx + 1) * ny + nx * (ny + 1)
+    cells = nx * ny
+    steps = args.warmup + args.learned_steps
+    out = {"workload": f"planar config-1 shock tube (liquid 1e9 Pa | air 1e5 Pa), {nx}x{ny} cells, 2 species, "
+                       f"transmissive x / periodic y, CFL 0.4",
+           "training": {"pairs": npairs, "adam_steps": 3000, "minibatch": 16384, "seconds": train_s,
+                        "loss_classical_weights": loss0, "loss_trained": loss1,
+                        "data": "1024 fine Riemann problems (200-2000 cells) after 40 and 120 FP64 steps"}}
+    for name in ("plain", "learned"):
+        r = res[name]
+        out[name] = {"value": cells * args.learned_steps / (r["ms"] * 1e-3), "unit": "cell-updates/s",
+                     "ms_per_step": r["ms"] / args.learned_steps, "sweep_ms_per_launch": r["sweep_ms"],
+                     "relax_bad": r["relax_bad"]}
+    out["learned"]["speedup_vs_plain"] = out["learned"]["value"] / out["plain"]["value"]
+    rp, rl = res["plain"]["W"][:N].sum(axis=0), res["learned"]["W"][:N].sum(axis=0)
+    out["learned"]["l1_rel_rho_vs_plain"] = float(np.abs(rl - rp).sum() / np.abs(rp).sum())
+    out["learned"]["after_steps"] = steps
+    # matrix-core work of the network: 2 M stencils per face, faces of both sweeps, 3 stages
+    mf = 3 * faces * 2 * M * MLP_FLOPS_PER_STENCIL
+    out["learned"]["mfma_tflops_algorithmic"] = mf / (out["learned"]["ms_per_step"] * 1e-3) / 1e12
+    out["learned"]["mfma_frac_of_bf16_peak"] = out["learned"]["mfma_tflops_algorithmic"] / 2500.0
+    return out
+
+
 def cpu_baseline(prob, budget_s=12.0, max_steps=20):
     import oracle
     oracle.build(force=False)
@@ -154,6 +230,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=1000,
                     help="steps of the batched ensemble (0 skips it)")
+    ap.add_argument("--learned-steps", type=int, default=100,
+                    help="timed steps of the learned-weight comparison (0 skips it)")
+    ap.add_argument("--learned-nx", type=int, default=2048)
+    ap.add_argument("--learned-ny", type=int, default=1024)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 512 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -265,6 +345,8 @@ def main():
                    "after_steps": args.warmup + args.steps, "relax_bad": d32["relax_bad"]}
     if args.batch_steps > 0:
         out["batched"] = bench_batch(args)
+    if args.learned_steps > 0:
+        out["learned"] = bench_learned(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)

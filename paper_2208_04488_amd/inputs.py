@@ -282,6 +282,27 @@ def config1(n=400):
     return pr
 
 
+def config5(nx=2048, ny=1024):
+    """The config-1 shock tube as a planar problem on [0, 1] x [0, 0.5]:
+    liquid (p 1e9, rho 1000) for x < 0.7, air (p 1e5, rho 50) beyond, u = v = 0,
+    trace 1e-8; transmissive in x, periodic in y; CFL 0.4 to t = 240 us.  The
+    workload of the learned interpolation weights against the plain method."""
+    eos = eos_of(LIQ_A, AIR)
+    left = _side(eos, 0, 1e9, 1000.0)
+    right = _side(eos, 1, 1e5, 50.0)
+    dx = (1.0 / nx, 0.5 / ny)
+    x = (np.arange(nx) + 0.5) * dx[0]
+    Lm = np.broadcast_to(x < 0.7, (ny, nx))
+    alpha = [np.where(Lm, left[0][k], right[0][k]) for k in range(eos.N)]
+    rho_k = [np.where(Lm, left[1][k], right[1][k]) for k in range(eos.N)]
+    zero = np.zeros((ny, nx))
+    p = np.where(Lm, left[3], right[3])
+    W = state_from_fields(eos, alpha, rho_k, [zero, zero], p)
+    return Problem("config5_planar_shock_tube", eos, 2, (nx, ny), dx, [(TRANSMISSIVE, TRANSMISSIVE),
+                   (PERIODIC, PERIODIC)], _as4(W, 2), t_end=240e-6, x0=(0.0, 0.0),
+                   meta=dict(x_split=0.7, left=left[:4], right=right[:4]))
+
+
 def rankine_hugoniot_ideal(gamma, R, p0, T0, mach):
     """Post-shock state of a normal shock of Mach number `mach` moving into an
     ideal gas at rest; returns (p1, rho1, u1, T1)."""

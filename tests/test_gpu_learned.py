@@ -329,3 +329,39 @@ def test_learned_gain_on_config1(H, trained):
     w = res["learned"][2]
     assert res["learned"][1] == 0 and np.isfinite(w).all() and (w[:2] >= 0).all()
     assert res["learned"][0] <= 1.5 * res["plain"][0]
+
+
+def test_learned_gain_on_config5_full_size(H, trained):
+    """The learned-weight workload at full size: the planar config-1 shock
+    tube on 2048 x 1024 cells to 240 us.  Every row must stay the same (the
+    problem is planar and y is periodic); L1 of the density of a row against
+    the exact solution for both methods."""
+    import torch
+    from oracle import exact_riemann as ER
+    prob = I.config5()
+    eos = prob.eos
+    L = dict(rho=1000.0, u=0.0, p=1e9, gamma=eos.gamma[0], pinf=eos.pinf[0])
+    R = dict(rho=50.0, u=0.0, p=1e5, gamma=eos.gamma[1], pinf=0.0)
+    x = (np.arange(prob.n[0]) + 0.5) * prob.dx[0]
+    rex, _, _ = ER.solve(x, prob.t_end, 0.7, L, R)
+    res = {}
+    for name, mlp in (("plain", None), ("learned", trained["p"])):
+        s = H.Solver(prob, mlp=mlp)
+        k = 0
+        while True:
+            s.step(cfl=prob.cfl, t_end=prob.t_end)
+            k += 1
+            if k % 200 == 0:
+                torch.cuda.synchronize()
+                if s.slot[4].item() >= prob.t_end:
+                    break
+        w, d = s.state(), s.diagnostics()
+        s.close()
+        rho = w[:2].sum(axis=0)[0]
+        assert d["relax_bad"] == 0 and np.isfinite(w).all() and (w[:2] >= 0).all()
+        assert np.abs(rho - rho[0]).max() <= 1e-9 * rho.max(), name   # rows identical
+        res[name] = np.abs(rho[0] - rex).sum() * prob.dx[0]
+        print(f"config5 {name}: {k} steps, L1(rho) vs exact {res[name]:.6e}")
+    # reported, not a win: at 2048 cells the plain method is ahead by about 10%
+    # (at 400 cells the learned weights are ahead by about 4%)
+    assert res["learned"] <= 1.25 * res["plain"]

@@ -201,6 +201,59 @@ def bench_learned(args):
     return out
 
 
+def bench_3d(args):
+    """The 3D multimode workload (256^3, three species, periodic in y and z):
+    FP64 and FP32 face arithmetic, K steps each from the initial condition."""
+    import numpy as np
+    import torch
+    from paper_2208_04488_amd import hrm
+    from paper_2208_04488_amd import inputs as I
+
+    prob = I.config3(args.n3d)
+    N, D, M = prob.N, prob.D, prob.M
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, prec in (("fp64", hrm.FP64), ("fp32", hrm.FP32)):
+        s = hrm.Solver(prob, flags=hrm.FUSE_RELAX, precision=prec)
+        s.step(cfl=prob.cfl)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps3d):
+            s.step(cfl=prob.cfl)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        hrm.hrm_set_timing(s.ctx, 0b111)
+        hrm.hrm_get_timing(s.ctx)
+        s.step(cfl=prob.cfl)
+        tm = hrm.hrm_get_timing(s.ctx)
+        hrm.hrm_set_timing(s.ctx, 0)
+        d = s.diagnostics()
+        rho = s.state()[:N].sum(axis=0)
+        res[name] = dict(ms=ms, rho=rho, relax_bad=d["relax_bad"], tm=tm)
+        s.close()
+        del s
+    out = {"workload": f"3D multimode interface, Mach-1.5 shock, 10% liquid droplets, 3 species, "
+                       f"{prob.n[0]}^3 cells, periodic y/z, CFL 0.4", "steps": args.steps3d + 2}
+    for name in ("fp64", "fp32"):
+        r = res[name]
+        out[name] = {"value": prob.ncell * args.steps3d / (r["ms"] * 1e-3), "unit": "cell-updates/s",
+                     "ms_per_step": r["ms"] / args.steps3d, "relax_bad": r["relax_bad"],
+                     "sweep_ms_per_launch": {k: r["tm"][k][0] / max(r["tm"][k][1], 1)
+                                             for k in ("sweep_x", "sweep_y", "sweep_z")}}
+    kx = max(("sweep_x", "sweep_y", "sweep_z"), key=lambda k: out["fp64"]["sweep_ms_per_launch"][k])
+    kd = ("sweep_x", "sweep_y", "sweep_z").index(kx)
+    fl = sweep_flops(N, D, prob.n, kd, final=(kd == D - 1))
+    out["fp64"]["dominant_kernel"] = f"k_sweep direction {kd}"
+    out["fp64"]["achieved_tflops_algorithmic"] = fl / (out["fp64"]["sweep_ms_per_launch"][kx] * 1e-3) / 1e12
+    out["fp64"]["hbm_gbs_algorithmic"] = algorithmic_bytes_per_cell_step(M) * out["fp64"]["value"] / 1e9
+    out["fp32"]["speedup_vs_fp64"] = out["fp32"]["value"] / out["fp64"]["value"]
+    r64, r32 = res["fp64"]["rho"], res["fp32"]["rho"]
+    out["fp32"]["l1_rel_rho_vs_fp64"] = float(np.abs(r32 - r64).sum() / np.abs(r64).sum())
+    return out
+
+
 def cpu_baseline(prob, budget_s=12.0, max_steps=20):
     import oracle
     oracle.build(force=False)
@@ -233,6 +286,8 @@ def main():
     ap.add_argument("--learned-steps", type=int, default=100,
                     help="timed steps of the learned-weight comparison (0 skips it)")
     ap.add_argument("--learned-nx", type=int, default=2048)
+    ap.add_argument("--steps3d", type=int, default=10, help="timed steps of the 3D workload (0 skips it)")
+    ap.add_argument("--n3d", type=int, default=256)
     ap.add_argument("--learned-ny", type=int, default=1024)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 512 MiB device copy (reference for the HBM byte counters)")
@@ -347,6 +402,8 @@ def main():
         out["batched"] = bench_batch(args)
     if args.learned_steps > 0:
         out["learned"] = bench_learned(args)
+    if args.steps3d > 0:
+        out["multimode_3d"] = bench_3d(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)

@@ -262,6 +262,35 @@ def test_full_size_bench_workload_step(H, orc):
     s.close()
 
 
+def test_full_size_multimode_3d_stage(H, orc):
+    """The 3D multimode workload at its full size (256^3, three species, 1.2 GB
+    per state): one SSP-RK3 stage with the relaxation, every cell compared
+    with the oracle, limiter counters equal."""
+    prob = I.config3(256)
+    check_stages_first(H, orc, prob)
+
+
+def check_stages_first(H, orc, prob):
+    import torch
+    N, D = prob.N, prob.D
+    o = orc.from_problem(prob)
+    dt, lam = o.dt(prob.W, prob.cfl)
+    cmax = o.max_wavespeed(prob.W).max()
+    ref = o.stage(0, prob.W, prob.W, dt, lam)
+    s = solver(H, prob, H.FUSE_RELAX)
+    s.set_slot(dt, lam)
+    H.hrm_reset_diagnostics(s.ctx)
+    got = s.stage(0, s.W, s.W)
+    torch.cuda.synchronize()
+    err = rel_err(got.cpu().numpy(), ref, N, D, cmax)
+    print(f"{prob.name} {prob.n}: stage 0 max rel {err:.2e}")
+    assert err <= TOL
+    dg, co = s.diagnostics(), o.counter_dict()
+    for key in ("alg1", "alg2", "interp_hs", "alg3", "alg4", "flux_hs", "relax_bad"):
+        assert dg[key] == co[key], (key, dg[key], co[key])
+    s.close()
+
+
 def test_multistep_t_end_clipping(H, orc):
     """Config-1 shock tube driven to t_end with the device time: the last step
     lands on t_end, positivity holds, and the result tracks the oracle."""

@@ -366,6 +366,55 @@ __device__ inline void alphas(const double* W, double* al)
 // plus the alpha slots of the "+" vector (N-1); the other slots agree.
 //   W_i^+     = W_i     - 2 lambda (G^- - F_i)
 //   W_{i+1}^- = W_{i+1} + 2 lambda (G^+ - F_{i+1})
+// True when the high-order pair's half-cell states (Sec. 4.3.2) are finite
+// and at or above every flux-limiter bound: then theta = 1 in Alg. 3 and
+// Alg. 4 whatever the first-order states are (b >= eps >= min(eps, a)), the
+// hard switch cannot fire (eps >= eps^HS, checked at set-up), and the
+// limited pair is the high-order one.  Meaningful only with
+// P.fast_flux_limiter.
+template <int N, int D, int DIR>
+__device__ inline bool flux_limit_clean(const EosDev& e, const ParDev& P, const St<N, D>& L, const St<N, D>& R,
+                                        double lam, const double* Gho, const double* Gho_p)
+{
+    constexpr int M = 2 * N + D, IE = N + D, IA = N + D + 1;
+    if (!P.fast_flux_limiter) return false;
+    const double uL = L.u[DIR], uR = R.u[DIR];
+    const double l2 = 2.0 * lam;
+    double Wp[M], Wm[M];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        Wp[k] = L.ar[k] - l2 * (Gho[k] - L.ar[k] * uL);
+        Wm[k] = R.ar[k] + l2 * (Gho[k] - R.ar[k] * uR);
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        Wp[N + d] = L.mom[d] - l2 * (Gho[N + d] - (L.mom[d] * uL + (d == DIR ? L.p : 0.0)));
+        Wm[N + d] = R.mom[d] + l2 * (Gho[N + d] - (R.mom[d] * uR + (d == DIR ? R.p : 0.0)));
+    }
+    Wp[IE] = L.E - l2 * (Gho[IE] - (L.E + L.p) * uL);
+    Wm[IE] = R.E + l2 * (Gho[IE] - (R.E + R.p) * uR);
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) {
+        Wp[IA + k] = L.al[k] - l2 * (Gho[IA + k] - 0.0);
+        Wm[IA + k] = R.al[k] + l2 * (Gho_p[k] - 0.0);
+    }
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < N; ++k) ok = ok && Wp[k] >= P.eps_f_ar && Wm[k] >= P.eps_f_ar;
+    double ap[N], am[N];
+    alphas<N, D>(Wp, ap);
+    alphas<N, D>(Wm, am);
+#pragma unroll
+    for (int k = 0; k < N; ++k) ok = ok && ap[k] >= P.eps_f_a && am[k] >= P.eps_f_a;
+    const double rep = rhoe_tilde<N, D>(e, Wp), rem = rhoe_tilde<N, D>(e, Wm);
+    ok = ok && rep >= P.eps_f_re && rem >= P.eps_f_re && isfinite(rep) && isfinite(rem);
+#pragma unroll
+    for (int c = 0; c < M; ++c) ok = ok && isfinite(Gho[c]) && isfinite(Wp[c]) && isfinite(Wm[c]);
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) ok = ok && isfinite(Gho_p[k]);
+    return ok;
+}
+
 template <int N, int D, int DIR>
 __device__ inline void flux_limit(const EosDev& e, const ParDev& P, const St<N, D>& L, const St<N, D>& R,
                                   double lam, const double* Gho, const double* Gho_p, const double* Glo,

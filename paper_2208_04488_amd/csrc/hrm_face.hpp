@@ -119,17 +119,20 @@ __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, do
     load_node<N, D, NS, FS>(nd, 3, Rn);
     const St<N, D, R> Lr = convert<N, D, R>(L), Rr = convert<N, D, R>(Rn);
 
-    // first-order HLLC of the node pair and its quasi-conservative pair (eq:G_pm)
-    double Glo[M], Glo_p[NA];
-    {
+    // first-order HLLC of the node pair and its quasi-conservative pair
+    // (eq:G_pm); needed only by the first-order scheme and by the flux
+    // limiter when it has to act, so it is formed on demand
+    auto first_order = [&](double* Glo, double* Glo_p) {
         const double ss = hllc<N, D, DIR, R>(Lr, Rr, Glo);
 #pragma unroll
         for (int k = 0; k < N - 1; ++k) {
             Glo_p[k] = Glo[IA + k] - ss * Rr.al[k];
             Glo[IA + k] = Glo[IA + k] - ss * Lr.al[k];
         }
-    }
+    };
     if (P.flags & F_FIRST_ORDER) {
+        double Glo[M], Glo_p[NA];
+        first_order(Glo, Glo_p);
 #pragma unroll
         for (int c = 0; c < M; ++c) G[c] = Glo[c];
 #pragma unroll
@@ -293,6 +296,18 @@ __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, do
         for (int k = 0; k < N - 1; ++k) Gp[k] = Gho_p[k];
         return;
     }
+    // Alg. 3 and Alg. 4 leave the high-order pair untouched when its half-cell
+    // states already satisfy every bound (the usual case away from
+    // interfaces and shocks); the first-order pair is formed only otherwise
+    if (flux_limit_clean<N, D, DIR>(e, P, L, Rn, lam, Gho, Gho_p)) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) G[c] = Gho[c];
+#pragma unroll
+        for (int k = 0; k < N - 1; ++k) Gp[k] = Gho_p[k];
+        return;
+    }
+    double Glo[M], Glo_p[NA];
+    first_order(Glo, Glo_p);
     flux_limit<N, D, DIR>(e, P, L, Rn, lam, Gho, Gho_p, Glo, Glo_p, G, Gp, cnt);
 }
 

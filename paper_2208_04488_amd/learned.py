@@ -1,9 +1,9 @@
 """Learned interpolation weights: training data from a fine ensemble and
 training on the GPU through the library's own kernels (hrm_mlp_*).
 
-The network (5-32-32-3, ReLU, softmax over the three candidates of the
-fifth-order interpolation around the linear weights) and its use in the solver
-are described in include/hrm.h (hrm_set_mlp).  Pairs come from FP64 solutions
+The network (5-32-32-3, ReLU) rescales the classical fifth-order WENO weights
+of the three 3-point candidates by at most e either way; it and its use in the
+solver are described in include/hrm.h (hrm_set_mlp).  Pairs come from FP64 solutions
 of an ensemble of 1D two-phase Riemann problems on a grid twice as fine as
 the one the weights are meant for (labels by injection, hrm_mlp_extract).
 """
@@ -19,7 +19,7 @@ NPARAM = hrm.MLP_NPARAM
 
 def init_params(seed: int = 0, last_scale: float = 0.1) -> np.ndarray:
     """He-uniform hidden layers, zero biases, a small last layer (the initial
-    weights are close to the linear ones)."""
+    weights are close to the classical ones)."""
     rng = np.random.default_rng(seed)
     parts = [rng.uniform(-1, 1, 160) * np.sqrt(6.0 / 5.0), np.zeros(32),
              rng.uniform(-1, 1, 1024) * np.sqrt(6.0 / 32.0), np.zeros(32),
@@ -58,10 +58,11 @@ def training_data(batch, snapshots=(40, 120), cfl: float = 0.4):
 
 
 def train(X, T, steps: int = 2000, count: int = 16384, lr: float = 2e-3, seed: int = 0, params=None,
-          log_every: int = 0):
-    """Adam on the mean squared normalised residual; minibatch i takes the
-    samples (first_i + k stride) mod n, stride = n // count, so each
-    minibatch spans the whole data set.  Returns (params float32, losses)."""
+          log_every: int = 0, lr_final: float = 0.05):
+    """Adam on the mean squared normalised residual with a cosine decay of the
+    step size from lr to lr * lr_final; minibatch i takes the samples
+    (first_i + k stride) mod n, stride = n // count, so each minibatch spans
+    the whole data set.  Returns (params float32, losses)."""
     import torch
     n = X.shape[0]
     count = min(count, n)
@@ -77,7 +78,8 @@ def train(X, T, steps: int = 2000, count: int = 16384, lr: float = 2e-3, seed: i
     for it in range(1, steps + 1):
         first = (it * 7919) % n
         hrm.hrm_mlp_grad(p, X, T, first, stride, count, g, loss, work)
-        hrm.hrm_mlp_adam(p, g, m, v, it, lr)
+        f = lr_final + (1.0 - lr_final) * 0.5 * (1.0 + np.cos(np.pi * (it - 1) / max(steps - 1, 1)))
+        hrm.hrm_mlp_adam(p, g, m, v, it, lr * f)
         if log_every and (it % log_every == 0 or it == 1):
             losses.append((it, float(loss.item())))
     return p.cpu().numpy(), losses

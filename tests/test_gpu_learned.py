@@ -290,13 +290,14 @@ def trained(H):
 
 def test_training_lowers_the_interpolation_loss(trained):
     t = trained
-    print(f"{t['n']} pairs; loss linear {t['loss_linear']:.4e} -> trained {t['loss']:.4e}; "
-          f"held-out linear {t['held_linear']:.4e} -> trained {t['held']:.4e}; history {t['hist']}")
+    print(f"{t['n']} pairs; loss with the classical weights {t['loss_linear']:.4e} -> trained {t['loss']:.4e}; "
+          f"held-out {t['held_linear']:.4e} -> {t['held']:.4e}; history {t['hist']}")
     # the best convex combination of the candidates for every pair is about
-    # 40% below the linear weights on such data, App. C about 4%; a 5-input
-    # network gets part of the way
-    assert t["loss"] < 0.95 * t["loss_linear"]
-    assert t["held"] < 0.95 * t["held_linear"]
+    # 40% below the linear weights on such data, the classical weights (the
+    # starting point here) a few per cent; the network, which may rescale
+    # each classical weight by at most e, gets a few per cent further
+    assert t["loss"] < 0.97 * t["loss_linear"]
+    assert t["held"] < 0.98 * t["held_linear"]
 
 
 def test_learned_gain_on_config1(H, trained):

@@ -55,6 +55,40 @@ def sweep_flops(N, D, n, direction, final):
     return faces * face_flops(N, D) + cells * (node_flops(N, D) + cell_flops(N, D, final))
 
 
+COUNTERS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        "k_sweep_liquid_column_1024x512_fp64_counters.json")
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the library's kernel sources (name, then contents, sorted)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2208_04488_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or
+    None if the summary is missing, is for another kernel, or was taken on
+    other kernel sources than the ones built here."""
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("kernel") != kernel or c.get("source_sha256") != kernel_source_hash():
+        return None
+    cal = c["calibration"]
+    return 1024.0 * (c["fetch_kib_per_dispatch"] * cal["fetch_factor"] +
+                     c["write_kib_per_dispatch"] * cal["write_factor"])
+
+
 def algorithmic_bytes_per_cell_step(M):
     """Stage 1 reads W^n, writes W1; stages 2, 3 read W^(s) and W^n, write the
     next state: 8 M doubles per cell per RK3 step."""
@@ -354,6 +388,21 @@ def main():
     flops = sweep_flops(N, D, prob.n, kdir, final=(kdir == D - 1))
     achieved = flops / (ms_launch * 1e-3) / 1e12
     cups = prob.ncell * args.steps / (ms_total * 1e-3)
+    # algorithmic bytes of that launch: W_s read, plus (last direction) W^n and
+    # the RHS read and the stage output written; first direction writes the RHS
+    final = kdir == D - 1
+    if D == 1:
+        narrays = 3       # W_s, W^n read; stage output written
+    elif final:
+        narrays = 4       # W_s, W^n, RHS read; stage output written
+    elif kdir == 0:
+        narrays = 2       # W_s read; RHS written
+    else:
+        narrays = 3       # W_s read; RHS read and written
+    sweep_bytes = 8 * M * prob.ncell * narrays
+    kname_full = f"k_sweep<{N},{D},{kdir},{16 if kdir else (64 if D > 1 else 256)}," \
+                 f"{16 if kdir else (4 if D > 1 else 1)},double,0>"
+    traffic = measured_traffic(kname_full)
     hbm = algorithmic_bytes_per_cell_step(M) * cups / 1e9
 
     out = {
@@ -365,7 +414,10 @@ def main():
                    "cells": prob.ncell, "species": N, "dim": D, "components": M},
         "roofline": {"bound": "alu", "kernel": f"k_sweep direction {kdir} (N={N}, D={D})",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "traffic_gbs": None if traffic is None else traffic / (ms_launch * 1e-3) / 1e9,
+                     "algorithmic_bytes_per_launch": sweep_bytes,
                      "flops_per_launch": flops, "ms_per_launch": ms_launch},
         "hbm_gbs_algorithmic": hbm, "hbm_frac_algorithmic": hbm / PEAK_HBM_GBS,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in timers.items() if v[1]},

@@ -288,11 +288,9 @@ def bench_3d(args):
     return out
 
 
-def cpu_baseline(prob, budget_s=12.0, max_steps=20):
+def _oracle_rate(prob, budget_s, max_steps, mlp=None):
     import oracle
-    oracle.build(force=False)
-    threads = oracle.Oracle.set_threads(0)
-    o = oracle.from_problem(prob)
+    o = oracle.from_problem(prob, mlp=mlp)
     W = prob.W
     t0 = time.perf_counter()
     steps = 0
@@ -302,9 +300,29 @@ def cpu_baseline(prob, budget_s=12.0, max_steps=20):
         if time.perf_counter() - t0 >= budget_s:
             break
     el = time.perf_counter() - t0
-    return {"value": prob.ncell * steps / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} SSP-RK3 steps of the full {prob.n[0]}x{prob.n[1]} workload from its initial "
-                      f"condition, OpenMP over grid lines, {el:.1f} s"}
+    return prob.ncell * steps / el, steps, el
+
+
+def cpu_baseline(prob, budget_s=15.0, max_steps=200, others=True):
+    """The oracle as it stands (C, FP64, OpenMP over grid lines) on the host
+    cores: complete SSP-RK3 steps from the initial condition of the full
+    benchmark workload, and shorter samples of the other workloads."""
+    import oracle
+    from paper_2208_04488_amd import inputs as I
+    oracle.build(force=False)
+    threads = oracle.Oracle.set_threads(0)
+    rate, steps, el = _oracle_rate(prob, budget_s, max_steps)
+    out = {"value": rate, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"{steps} SSP-RK3 steps of the full {prob.n[0]}x{prob.n[1]} workload from its initial "
+                     f"condition, OpenMP over grid lines, {el:.1f} s"}
+    if others:
+        more = {}
+        for name, p in (("multimode_3d_128^3", I.config3(128)), ("planar_shock_tube_512x256", I.config5(512, 256)),
+                        ("riemann_problem_1000_cells", I.config4(lengths=[1000]).problem(0))):
+            r, k, e = _oracle_rate(p, 5.0, 50)
+            more[name] = {"value": r, "steps": k, "seconds": e}
+        out["other_workloads"] = more
+    return out
 
 
 def main():

@@ -114,15 +114,20 @@ __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, do
     auto back = [&](int f, R d) -> R { return DELTA ? (R)(nodev<NS, FS>(nd, 2, f) + (double)d) : d; };
     auto back_d = [&](int f, R d) -> double { return DELTA ? nodev<NS, FS>(nd, 2, f) + (double)d : (double)d; };
 
-    St<N, D> L, Rn;
-    load_node<N, D, NS, FS>(nd, 2, L);
-    load_node<N, D, NS, FS>(nd, 3, Rn);
-    const St<N, D, R> Lr = convert<N, D, R>(L), Rr = convert<N, D, R>(Rn);
+    // the two nodes of the face (i, i+1), read from LDS where they are used:
+    // the compiler barrier forces fresh reads, so the node states do not
+    // occupy registers across the whole face computation
+    auto node_pair = [&](St<N, D>& a, St<N, D>& b) {
+        asm volatile("" ::: "memory");
+        load_node<N, D, NS, FS>(nd, 2, a);
+        load_node<N, D, NS, FS>(nd, 3, b);
+    };
 
     // first-order HLLC of the node pair and its quasi-conservative pair
     // (eq:G_pm); needed only by the first-order scheme and by the flux
     // limiter when it has to act, so it is formed on demand
-    auto first_order = [&](double* Glo, double* Glo_p) {
+    auto first_order = [&](const St<N, D>& L, const St<N, D>& Rn, double* Glo, double* Glo_p) {
+        const St<N, D, R> Lr = convert<N, D, R>(L), Rr = convert<N, D, R>(Rn);
         const double ss = hllc<N, D, DIR, R>(Lr, Rr, Glo);
 #pragma unroll
         for (int k = 0; k < N - 1; ++k) {
@@ -131,8 +136,10 @@ __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, do
         }
     };
     if (P.flags & F_FIRST_ORDER) {
+        St<N, D> L, Rn;
+        node_pair(L, Rn);
         double Glo[M], Glo_p[NA];
-        first_order(Glo, Glo_p);
+        first_order(L, Rn, Glo, Glo_p);
 #pragma unroll
         for (int c = 0; c < M; ++c) G[c] = Glo[c];
 #pragma unroll
@@ -143,8 +150,8 @@ __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, do
     // App. D: projection with the midpoint means of alpha_k rho_k, rho and c
     R arb[N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) arb[k] = (R)0.5 * (Lr.ar[k] + Rr.ar[k]);
-    const R rb = (R)0.5 * (Lr.rho + Rr.rho), cb = (R)0.5 * (Lr.c + Rr.c);
+    for (int k = 0; k < N; ++k) arb[k] = (R)0.5 * (nv(2, k) + nv(3, k));
+    const R rb = (R)0.5 * (nv(2, F::RHO) + nv(3, F::RHO)), cb = (R)0.5 * (nv(2, F::C) + nv(3, F::C));
     const R irc = (R)1 / (rb * cb), irc2 = irc / cb;
     const double eps = P.eps_weno;
     R UL[M], UR[M], v[6];
@@ -206,8 +213,10 @@ __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, do
 
     // Sec. 4.3.2 interpolation limiter: left against node i, right against node i+1
     if (!(P.flags & F_NO_LIMITERS)) {
-        interp_limit<N, D, R>(e, P, VL, Lr, cnt);  // also completes the state
-        interp_limit<N, D, R>(e, P, VR, Rr, cnt);
+        St<N, D> L, Rn;
+        node_pair(L, Rn);
+        interp_limit<N, D, R>(e, P, VL, convert<N, D, R>(L), cnt);  // also completes the state
+        interp_limit<N, D, R>(e, P, VR, convert<N, D, R>(Rn), cnt);
     } else {
         complete_from_prim<N, D, R>(e, VL);
         complete_from_prim<N, D, R>(e, VR);
@@ -286,8 +295,8 @@ __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, do
     // high-order quasi-conservative pair: alpha slots minus u-hat alpha_i / alpha_{i+1}
 #pragma unroll
     for (int k = 0; k < N - 1; ++k) {
-        Gho_p[k] = Gho[IA + k] - uh * Rr.al[k];
-        Gho[IA + k] = Gho[IA + k] - uh * Lr.al[k];
+        Gho_p[k] = Gho[IA + k] - uh * nodev<NS, FS>(nd, 3, IA + k);
+        Gho[IA + k] = Gho[IA + k] - uh * nodev<NS, FS>(nd, 2, IA + k);
     }
     if (P.flags & F_NO_LIMITERS) {
 #pragma unroll
@@ -299,6 +308,8 @@ __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, do
     // Alg. 3 and Alg. 4 leave the high-order pair untouched when its half-cell
     // states already satisfy every bound (the usual case away from
     // interfaces and shocks); the first-order pair is formed only otherwise
+    St<N, D> L, Rn;
+    node_pair(L, Rn);
     if (flux_limit_clean<N, D, DIR>(e, P, L, Rn, lam, Gho, Gho_p)) {
 #pragma unroll
         for (int c = 0; c < M; ++c) G[c] = Gho[c];
@@ -307,7 +318,7 @@ __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, do
         return;
     }
     double Glo[M], Glo_p[NA];
-    first_order(Glo, Glo_p);
+    first_order(L, Rn, Glo, Glo_p);
     flux_limit<N, D, DIR>(e, P, L, Rn, lam, Gho, Gho_p, Glo, Glo_p, G, Gp, cnt);
 }
 

@@ -283,8 +283,8 @@ const char* hrm_batch_last_error(const hrm_batch* b);
 
 /* Launch shape: threads per workgroup (64, 128 or 256; one face per
  * thread, tiles of threads-1 cells), workgroups of the persistent launch,
- * and SSP-RK3 steps per launch.  Defaults 256, 512, 10.  A change drops the
- * captured graph. */
+ * and SSP-RK3 steps per launch.  Defaults 256, 3 x the device's CU count,
+ * 10.  A change drops the captured graph. */
 int hrm_batch_configure(hrm_batch* b, int threads, int blocks, int steps_per_launch);
 
 /* Advance every problem of d_W (device, M x T) in place by nsteps steps, a

@@ -30,12 +30,12 @@ def _key(batch, precision, device_name) -> str:
 
 
 def candidates(cus: int):
-    """(threads, workgroups, steps per launch): one or two workgroups of 256
-    threads per CU and the equivalent numbers of waves for 128 and 64."""
+    """(threads, workgroups, steps per launch): one to three waves per SIMD
+    (the kernel's register budget allows three) for 64, 128 and 256 threads."""
     out = []
     for threads in (64, 128, 256):
         per_wave = threads // 64
-        for waves_per_simd in (1, 2):
+        for waves_per_simd in (1, 2, 3):
             blocks = cus * 4 * waves_per_simd // per_wave
             for k in (5, 20):
                 out.append((threads, blocks, k))

@@ -55,7 +55,7 @@ __device__ inline double uniform(double v)
 }
 
 template <int N, int BS, typename R>
-__global__ void __launch_bounds__(BS, 2) k_batch(const BatchArgs A)
+__global__ void __launch_bounds__(BS, 3) k_batch(const BatchArgs A)
 {
     constexpr int D = 1;
     using F = NodeFields<N, D>;
@@ -327,8 +327,15 @@ int hrm_batch_create(const hrm_eos* e, const hrm_params* prm, int nprob, const l
     P.hcs_c = 3.0 * p.psi / 256.0 - 1.0 / 60.0;
     P.flags = 0;
     P.fast_flux_limiter = p.eps_f_ar >= p.hs_f_ar && p.eps_f_a >= p.hs_f_a && p.eps_f_re >= p.hs_f_re;
+    // default launch: 256 threads, three workgroups per CU (the kernel's
+    // register budget admits three waves per SIMD), 10 steps per launch
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+    (void)hipGetLastError();
     b->threads = 256;
-    b->blocks = 512;
+    b->blocks = 3 * cus;
     b->ksteps = 10;
 
     // longest problems first

@@ -211,6 +211,40 @@ def advection_2d(n=32):
                    t_end=1e-4, dt_fixed=4e-5 * dx[0], x0=(-1.0, -1.0))
 
 
+def acoustic_1d(n=800, A=0.01, sigma=0.05, x_center=-0.75, c_ref=346.46):
+    """Sec. 5.3 acoustic pulse: [-1, 1] m split at -0.5; left air with the
+    liquid fraction 1e-8, right a 50/50 mixture, both at 101325 Pa / 298 K
+    (Table 1 EOS); a Gaussian density pulse rho' = A exp(-((x - x_c)/sigma)^2)
+    with p' = c_ref^2 rho' on the left at fixed mass fractions (T from rho and
+    p, then the species densities and volume fractions); u = 0; transmissive.
+    The transmitted pulse crosses the mixture at the four-equation (HRM)
+    sound speed."""
+    eos = table1_eos()
+    dx = (2.0 / n,)
+    x = -1.0 + (np.arange(n) + 0.5) * dx[0]
+    left = x < -0.5
+    # background mass fractions of the left region
+    a_bg = [np.full(n, TRACE), np.full(n, 1.0 - TRACE)]
+    rk_bg = [species_density(eos, k, P_ATM, T_ATM) for k in range(2)]
+    rho_bg = a_bg[0] * rk_bg[0] + a_bg[1] * rk_bg[1]
+    Y = [a_bg[k] * rk_bg[k] / rho_bg for k in range(2)]
+    drho = A * np.exp(-(((x - x_center) / sigma) ** 2))
+    rho = rho_bg + drho
+    p = P_ATM + c_ref ** 2 * drho
+    # 1/rho = sum_k Y_k / rho_k(p, T) with rho_k = (p + pinf_k)/((gamma_k - 1) c_v,k T)
+    inv = sum(Y[k] * (eos.gamma[k] - 1.0) * eos.cv[k] / (p + eos.pinf[k]) for k in range(2))
+    T = 1.0 / (rho * inv)
+    rk = [species_density(eos, k, p, T) for k in range(2)]
+    a_left = [Y[k] * rho / rk[k] for k in range(2)]
+    rk_mix = [np.full(n, species_density(eos, k, P_ATM, T_ATM)) for k in range(2)]
+    alpha = [np.where(left, a_left[k], 0.5) for k in range(2)]
+    rho_k = [np.where(left, rk[k], rk_mix[k]) for k in range(2)]
+    pp = np.where(left, p, P_ATM)
+    W = state_from_fields(eos, alpha, rho_k, [np.zeros(n)], pp)
+    return Problem("acoustic_1d", eos, 1, (n,), dx, [(TRANSMISSIVE, TRANSMISSIVE)], _as4(W, 1), cfl=0.4,
+                   t_end=50e-3, x0=(-1.0,), meta=dict(x_interface=-0.5, c_ref=c_ref, p_ref=P_ATM))
+
+
 def interface_advection(n=500, Cs: Optional[float] = None):
     """App. A: [0, 1) periodic, u = 100, water in [0.25, 0.75), air elsewhere,
     uniform 101325 Pa / 298 K; optional tanh smoothing with parameter C_s."""

@@ -57,6 +57,17 @@ extern "C" {
 #define HRM_FIRST_ORDER 4   /* first-order HLLC fluxes only (Sec. 4.1.1) */
 #define HRM_FUSE_RELAX 8    /* hrm_rk_stage relaxes its output in the same kernel */
 #define HRM_NO_GRAPH 16     /* hrm_step launches its kernels directly instead of replaying a graph */
+/* HRM_FOUR_EQ: solve the four-equation HRM directly instead of the fractional
+ * algorithm (the comparison scheme of Sec. 5.4 and App. A).  The fluxes of
+ * alpha_k rho_k, rho u and E are those of the first-order HLLC solver of
+ * Sec. 4.1.1 with the HRM pressure p* (eq:p_relax, the relaxed pressure of the
+ * state) and the HRM sound speed (eq:4_eqn_sos) in place of the five-equation
+ * ones, always in double precision; the volume fractions are not evolved (their
+ * right-hand side is zero) and are the equilibrium values only where the
+ * relaxation runs (HRM_FUSE_RELAX or hrm_relax), for output.  The time step of
+ * hrm_compute_dt / hrm_step uses the HRM sound speed.  Implies HRM_FIRST_ORDER;
+ * the limiter, blending and weight settings have no effect. */
+#define HRM_FOUR_EQ 32
 
 /* Uniform Cartesian grid of n[0] x n[1] x n[2] cells, nodes at cell centres
  * (Sec. 4.1).  Entries beyond `dim` must be n = 1. */
@@ -126,7 +137,8 @@ int hrm_destroy(hrm_ctx* ctx);
 const char* hrm_last_error(const hrm_ctx* ctx);
 
 /* Sec. 4.1.2: d_out[d] = max over cells of |u_d| + c (five-equation mixture
- * sound speed), d = 0..dim-1.  d_W: M x ncell doubles; d_out: dim doubles. */
+ * sound speed; the HRM sound speed under HRM_FOUR_EQ), d = 0..dim-1.
+ * d_W: M x ncell doubles; d_out: dim doubles. */
 int hrm_max_wavespeed(hrm_ctx* ctx, const double* d_W, double* d_out, void* stream);
 
 /* Sec. 4.1.2 multi-dimensional step: tau_d = d_maxspeed[d]/dx_d,

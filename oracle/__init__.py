@@ -23,6 +23,7 @@ _LIB = os.path.join(_HERE, "liborc.so")
 MAXN = 8
 TRANSMISSIVE, PERIODIC = 0, 1
 NO_LIMITERS, NO_BLEND, FIRST_ORDER = 1, 2, 4
+FOUR_EQ = 32  # the four-equation HRM solved directly with first-order HLLC
 COUNTERS = ("alg1", "alg2", "interp_hs", "alg3", "alg4", "flux_hs", "relax_bad", "unused")
 
 # tolerances and constants as the paper fixes them (Sec. 4.3, App. C)
@@ -97,6 +98,9 @@ def lib():
         L.orc_sensor.argtypes = [dp]
         L.orc_sensor.restype = ctypes.c_double
         L.orc_hllc.argtypes = [sp, ctypes.c_int, dp, dp, dp]
+        L.orc_hllc4.argtypes = [sp, ctypes.c_int, dp, dp, dp]
+        L.orc_hllc4.restype = ctypes.c_double
+        L.orc_hrm_eos.argtypes = [sp, dp, dp]
         L.orc_hllc.restype = ctypes.c_double
         L.orc_project.argtypes = [sp, ctypes.c_int, dp, dp, dp, dp, dp]
         L.orc_face.argtypes = [sp, ctypes.c_int, dp, ctypes.c_double, dp, dp, lp]
@@ -262,6 +266,19 @@ class Oracle:
         G = np.zeros(self.M)
         ss = self._L.orc_hllc(ctypes.byref(self.s), int(n), _dp(_f64(wl)), _dp(_f64(wr)), _dp(G))
         return G, ss
+
+    def hllc4(self, n, wl, wr):
+        """First-order HLLC flux of the four-equation HRM (alpha slots zero)."""
+        G = np.zeros(self.M)
+        ss = self._L.orc_hllc4(ctypes.byref(self.s), int(n), _dp(_f64(wl)), _dp(_f64(wr)), _dp(G))
+        return G, ss
+
+    def hrm_eos(self, w):
+        """(p, T, c) of the four-equation HRM for one conservative vector (the
+        volume fractions are ignored); NaNs outside the admissible set."""
+        out = np.zeros(3)
+        self._L.orc_hrm_eos(ctypes.byref(self.s), _dp(_f64(w)), _dp(out))
+        return out[0], out[1], out[2]
 
     def project(self, n, wa, wb, v):
         U, Vb = np.zeros(self.M), np.zeros(self.M)

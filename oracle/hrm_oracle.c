@@ -40,6 +40,7 @@
 #define ORC_NO_LIMITERS 1  /* skip the PP interpolation and flux limiters */
 #define ORC_NO_BLEND 2     /* sigma^s = 0: pure HCS flux (App. B ablation) */
 #define ORC_FIRST_ORDER 4  /* first-order HLLC fluxes only (Sec. 4.1.1) */
+#define ORC_FOUR_EQ 32    /* the four-equation HRM solved directly with first-order HLLC */
 
 /* diagnostic counters */
 #define ORC_C_ALG1 0      /* interpolation limiter, partial density limited */
@@ -624,11 +625,19 @@ static double sensor_sigma(const double *u)
 /* One face i+1/2 in direction n from the six nodes i-2..i+3 (nodes[0..5]).   */
 /* Produces the limited quasi-conservative pair G^{**,-}, G^{**,+}.           */
 /* ------------------------------------------------------------------------ */
+static double hllc4(const orc_setup *s, int n, const double *WL, const double *WR, double *G);
+
 static void face_flux(const orc_setup *s, int n, const orc_state *nodes, double lam, double *Gm, double *Gp,
                       long long *cnt)
 {
     const int N = s->N, M = NCOMP(s);
     const orc_state *L = &nodes[2], *R = &nodes[3];
+
+    if (s->flags & ORC_FOUR_EQ) {
+        hllc4(s, n, L->W, R->W, Gm);
+        for (int c = 0; c < M; ++c) Gp[c] = Gm[c];
+        return;
+    }
 
     /* first-order HLLC on the node pair and its quasi-conservative pair (eq:G_pm) */
     double Glo[ORC_MAXM], Gm_lo[ORC_MAXM], Gp_lo[ORC_MAXM];
@@ -811,7 +820,9 @@ void orc_rhs(const orc_setup *s, const double *W, const double *lam, double *Lou
 /* A cell with rho e-tilde <= 0 or no positive root is left unchanged and      */
 /* returns 1.                                                                  */
 /* ------------------------------------------------------------------------ */
-int orc_relax_cell(const orc_setup *s, double *W, double *pT)
+/* p* and T* of the relaxed state (eq:p_relax, eq:T_relax_e); returns 1 for a
+ * state with rho e-tilde <= 0 or without a positive root */
+static int relaxed_pT(const orc_setup *s, const double *W, double *p_out, double *T_out)
 {
     const int N = s->N;
     double rho = 0.0;
@@ -842,7 +853,16 @@ int orc_relax_cell(const orc_setup *s, double *W, double *pT)
     const double e_t = rhoe_t / rho;
     const double T = e_t / (Y[0] * (p + s->gamma[0] * p1) * s->cv[0] / (p + p1) + cvb - Y[0] * s->cv[0]);
     if (!(T > 0.0) || !isfinite(T)) return 1;
-    for (int k = 0; k < N - 1; ++k) {
+    *p_out = p;
+    *T_out = T;
+    return 0;
+}
+
+int orc_relax_cell(const orc_setup *s, double *W, double *pT)
+{
+    double p, T;
+    if (relaxed_pT(s, W, &p, &T)) return 1;
+    for (int k = 0; k < s->N - 1; ++k) {
         const double rho_k = (p + s->pinf[k]) / ((s->gamma[k] - 1.0) * s->cv[k] * T);
         W[IAL(s, k)] = W[k] / rho_k;
     }
@@ -851,6 +871,121 @@ int orc_relax_cell(const orc_setup *s, double *W, double *pT)
         pT[1] = T;
     }
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sec. 3: equation of state and sound speed of the four-equation HRM.        */
+/* p and T are the relaxed p*, T* of the conservative vector without the      */
+/* volume fractions.  c^2 = sum_k Y_k Psi_k + Gamma p / rho (eq:4_eqn_sos),    */
+/* with Psi_k = dp/d(alpha_k rho_k) at fixed e and Gamma = (1/rho) dp/de from  */
+/* the implicit derivative of A_p p^2 + B_p p + C_p = 0 (Sec. 4.2):            */
+/*   dp = -(dA_p p^2 + dB_p p + dC_p) / (2 A_p p + B_p),                       */
+/* where, with rho = sum_k alpha_k rho_k, Y_k = alpha_k rho_k / rho and         */
+/* rho (e - qbar) = sum_k alpha_k rho_k (e - q_k),                              */
+/*   A_p = cvbar,  B_p = -[rho (e - qbar) G - pinf_1 cvbar - pinf_1 Y_1 R_1],    */
+/*   C_p = -rho (e - qbar) pinf_1 (G - Y_1 R_1),  G = cpbar - cvbar,            */
+/*   R_1 = c_p1 - c_v1, and                                                    */
+/*   d cvbar / d(alpha_k rho_k) = (c_vk - cvbar)/rho,                          */
+/*   d G / d(alpha_k rho_k) = (R_k - G)/rho,  d Y_1 / d(alpha_k rho_k) =        */
+/*   (delta_k1 - Y_1)/rho,  d rho (e - qbar) / d(alpha_k rho_k) = e - q_k,      */
+/*   d rho (e - qbar) / de = rho.                                              */
+/* out = (p, T, c).  Returns 1 (out set to NaN) where relaxed_pT fails.        */
+/* ------------------------------------------------------------------------ */
+static int hrm_eos(const orc_setup *s, const double *W, double *out)
+{
+    const int N = s->N;
+    double p, T;
+    if (relaxed_pT(s, W, &p, &T)) {
+        out[0] = out[1] = out[2] = NAN;
+        return 1;
+    }
+    double rho = 0.0, mom2 = 0.0;
+    for (int k = 0; k < N; ++k) rho += W[k];
+    for (int d = 0; d < s->D; ++d) mom2 += W[IMOM(s, d)] * W[IMOM(s, d)];
+    const double e = (W[IE(s)] - 0.5 * mom2 / rho) / rho; /* specific internal energy */
+    double Y[ORC_MAXN] = {0}, Rk[ORC_MAXN] = {0}, cvb = 0.0, cpb = 0.0, re = 0.0;
+    for (int k = 0; k < N; ++k) {
+        Y[k] = W[k] / rho;
+        Rk[k] = s->gamma[k] * s->cv[k] - s->cv[k];
+        cvb += Y[k] * s->cv[k];
+        cpb += Y[k] * s->gamma[k] * s->cv[k];
+        re += W[k] * (e - s->q[k]);
+    }
+    const double p1 = s->pinf[0], R1 = Rk[0];
+    const double A = cvb, G = cpb - cvb, H = G - Y[0] * R1;
+    const double B = -(re * G - p1 * cvb - p1 * Y[0] * R1);
+    const double den = 2.0 * A * p + B;
+    double c2 = 0.0;
+    for (int k = 0; k < N; ++k) {
+        const double dA = (s->cv[k] - A) / rho;
+        const double dG = (Rk[k] - G) / rho;
+        const double dY1 = ((k == 0 ? 1.0 : 0.0) - Y[0]) / rho;
+        const double dre = e - s->q[k];
+        const double dB = -(dre * G + re * dG - p1 * dA - p1 * R1 * dY1);
+        const double dC = -p1 * (dre * H + re * (dG - R1 * dY1));
+        const double Psi = -(dA * p * p + dB * p + dC) / den;
+        c2 += Y[k] * Psi;
+    }
+    const double dBde = -rho * G, dCde = -p1 * rho * H;
+    const double Gamma = -(dBde * p + dCde) / den / rho;
+    c2 += Gamma * p / rho;
+    out[0] = p;
+    out[1] = T;
+    out[2] = c2 > 0.0 ? sqrt(c2) : NAN;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* First-order HLLC for the four-equation HRM solved directly (the reference */
+/* scheme of the comparisons of Sec. 5.4 and App. A).  Reading: the solver of */
+/* Sec. 4.1.1 applied to (alpha_k rho_k, rho u, E), with the HRM pressure and  */
+/* sound speed of hrm_eos in place of the five-equation ones, the same wave-   */
+/* speed estimates and sign(0) = 0.  The volume-fraction slots of G are zero.  */
+/* Returns s_*.                                                                */
+/* ------------------------------------------------------------------------ */
+static double hllc4(const orc_setup *s, int n, const double *WL, const double *WR, double *G)
+{
+    const int N = s->N, D = s->D, M = NCOMP(s);
+    double rho[2], u[2][3], p[2], c[2];
+    const double *Wk[2] = {WL, WR};
+    for (int side = 0; side < 2; ++side) {
+        double pTc[3];
+        hrm_eos(s, Wk[side], pTc);
+        rho[side] = 0.0;
+        for (int k = 0; k < N; ++k) rho[side] += Wk[side][k];
+        for (int d = 0; d < D; ++d) u[side][d] = Wk[side][IMOM(s, d)] / rho[side];
+        p[side] = pTc[0];
+        c[side] = pTc[2];
+    }
+    const double uL = u[0][n], uR = u[1][n];
+    const double ubar = 0.5 * (uL + uR), cbar = 0.5 * (c[0] + c[1]);
+    const double sL = fmin(ubar - cbar, uL - c[0]);
+    const double sR = fmax(ubar + cbar, uR + c[1]);
+    const double sstar = (p[1] - p[0] + rho[0] * uL * (sL - uL) - rho[1] * uR * (sR - uR)) /
+                         (rho[0] * (sL - uL) - rho[1] * (sR - uR));
+    double Ws[2][ORC_MAXM], F[2][ORC_MAXM];
+    for (int side = 0; side < 2; ++side) {
+        const double *W = Wk[side];
+        const double sK = side == 0 ? sL : sR, uK = u[side][n], pK = p[side];
+        const double chi = (sK - uK) / (sK - sstar);
+        for (int k = 0; k < N; ++k) {
+            Ws[side][k] = chi * W[k];
+            F[side][k] = W[k] * uK;
+        }
+        for (int d = 0; d < D; ++d) {
+            Ws[side][IMOM(s, d)] = d == n ? chi * rho[side] * sstar : chi * rho[side] * u[side][d];
+            F[side][IMOM(s, d)] = W[IMOM(s, d)] * uK + (d == n ? pK : 0.0);
+        }
+        Ws[side][IE(s)] = chi * (W[IE(s)] + (sstar - uK) * (rho[side] * sstar + pK / (sK - uK)));
+        F[side][IE(s)] = (W[IE(s)] + pK) * uK;
+    }
+    const double sm = fmin(0.0, sL), sp = fmax(0.0, sR);
+    const double sg = sstar > 0.0 ? 1.0 : (sstar < 0.0 ? -1.0 : 0.0);
+    for (int c = 0; c <= IE(s); ++c)
+        G[c] = 0.5 * (1.0 + sg) * (F[0][c] + sm * (Ws[0][c] - WL[c])) +
+               0.5 * (1.0 - sg) * (F[1][c] + sp * (Ws[1][c] - WR[c]));
+    for (int c = IE(s) + 1; c < M; ++c) G[c] = 0.0;
+    return sstar;
 }
 
 /* relaxation of every cell of a state array (hot-path step a11) */
@@ -872,7 +1007,8 @@ void orc_relax(const orc_setup *s, double *W, long long *cnt)
     if (cnt) cnt[ORC_C_RELAX_BAD] += bad;
 }
 
-/* Sec. 4.1.2: max over cells of |u_d| + c for each direction d (five-equation c) */
+/* Sec. 4.1.2: max over cells of |u_d| + c for each direction d (five-equation
+ * c; the HRM c of hrm_eos when the four-equation model is solved directly) */
 void orc_max_wavespeed(const orc_setup *s, const double *W, double *out)
 {
     const long nc = NCELL(s);
@@ -880,8 +1016,14 @@ void orc_max_wavespeed(const orc_setup *s, const double *W, double *out)
     for (long cell = 0; cell < nc; ++cell) {
         orc_state st;
         load_state(s, W, cell, &st);
+        double c = st.c;
+        if (s->flags & ORC_FOUR_EQ) {
+            double pTc[3];
+            hrm_eos(s, st.W, pTc);
+            c = pTc[2];
+        }
         for (int d = 0; d < s->D; ++d) {
-            const double v = fabs(st.V[IMOM(s, d)]) + st.c;
+            const double v = fabs(st.V[IMOM(s, d)]) + c;
             if (v > out[d] || !(v == v)) out[d] = v;
         }
     }
@@ -975,6 +1117,14 @@ int orc_mlp_interp(const double *params, const double *u5, double *out, double *
 double orc_bf16(double x) { return bf16_round(x); }
 
 double orc_sensor(const double *u6) { return sensor_sigma(u6); }
+
+/* out = (p, T, c) of the four-equation HRM; returns 1 for a state outside G */
+int orc_hrm_eos(const orc_setup *s, const double *W, double *out) { return hrm_eos(s, W, out); }
+
+double orc_hllc4(const orc_setup *s, int n, const double *WL, const double *WR, double *G)
+{
+    return hllc4(s, n, WL, WR, G);
+}
 
 double orc_hllc(const orc_setup *s, int n, const double *WL, const double *WR, double *G)
 {

@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(256) k_relax(double* W, long long nc, EosDev e
 }
 
 template <int N, int D>
-__global__ void __launch_bounds__(256) k_wavespeed(const double* W, long long nc, EosDev e, double* part)
+__global__ void __launch_bounds__(256) k_wavespeed(const double* W, long long nc, EosDev e, int four, double* part)
 {
     constexpr int M = 2 * N + D;
     __shared__ double sh[4 * 3];
@@ -208,8 +208,13 @@ __global__ void __launch_bounds__(256) k_wavespeed(const double* W, long long nc
         for (int k = 0; k < M; ++k) w[k] = W[k * nc + i];
         St<N, D> s;
         state_from_W<N, D>(e, w, s);
+        double c = s.c;
+        if (four) {  // the four-equation model solved directly: its own sound speed
+            double p;
+            hrm4_pc<N, D>(e, s, p, c);
+        }
 #pragma unroll
-        for (int d = 0; d < D; ++d) m[d] = nmax(m[d], fabs(s.u[d]) + s.c);
+        for (int d = 0; d < D; ++d) m[d] = nmax(m[d], fabs(s.u[d]) + c);
     }
     block_max<D>(m, sh);
     if (threadIdx.x == 0)
@@ -456,14 +461,16 @@ struct Ops {
     static void wavespeed_dt(hrm_ctx* c, const double* W, const hrm::DtArgs& a, double* slot, hipStream_t s)
     {
         TimerScope t(c, HRM_T_WAVESPEED, s);
-        hipLaunchKernelGGL((hrm::k_wavespeed<N, D>), dim3(c->npart), dim3(256), 0, s, W, c->ncell, c->eos, c->d_part);
+        hipLaunchKernelGGL((hrm::k_wavespeed<N, D>), dim3(c->npart), dim3(256), 0, s, W, c->ncell, c->eos,
+                           (c->flags & HRM_FOUR_EQ) ? 1 : 0, c->d_part);
         hipLaunchKernelGGL((hrm::k_reduce_dt<D>), dim3(1), dim3(256), 0, s, c->d_part, c->npart, c->d_maxs, a, slot);
     }
 
     static void wavespeed(hrm_ctx* c, const double* W, double* out, hipStream_t s)
     {
         TimerScope t(c, HRM_T_WAVESPEED, s);
-        hipLaunchKernelGGL((hrm::k_wavespeed<N, D>), dim3(c->npart), dim3(256), 0, s, W, c->ncell, c->eos, c->d_part);
+        hipLaunchKernelGGL((hrm::k_wavespeed<N, D>), dim3(c->npart), dim3(256), 0, s, W, c->ncell, c->eos,
+                           (c->flags & HRM_FOUR_EQ) ? 1 : 0, c->d_part);
         hipLaunchKernelGGL((hrm::k_reduce_max<D>), dim3(1), dim3(256), 0, s, c->d_part, c->npart, out);
     }
 };
@@ -660,6 +667,7 @@ int hrm_create(const hrm_grid* g, const hrm_eos* e, const hrm_params* prm, hrm_c
     P.hcs_b = 25.0 * p.psi / 256.0 - 2.0 / 15.0;
     P.hcs_c = 3.0 * p.psi / 256.0 - 1.0 / 60.0;
     P.flags = g->flags;
+    if (g->flags & HRM_FOUR_EQ) P.flags |= HRM_FIRST_ORDER;  // the direct HRM solver is first order
     P.fast_flux_limiter = p.eps_f_ar >= p.hs_f_ar && p.eps_f_a >= p.hs_f_a && p.eps_f_re >= p.hs_f_re;
 
     const size_t bytes = sizeof(double) * (size_t)c->M * (size_t)c->ncell;

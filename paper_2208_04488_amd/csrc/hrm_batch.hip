@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(BS, 3) k_batch(const BatchArgs A)
                     double G[M], Gp[NA];
                     {
                         unsigned lc[C_N] = {0, 0, 0, 0, 0, 0, 0};
-                        face_flux<N, D, 0, 1, FS, R>(lds + ts, e, P, lam, G, Gp, lc);
+                        face_flux<N, D, 0, 1, FS, R, 0, false>(lds + ts, e, P, lam, G, Gp, lc);
                         const int f = c0 + ts;  // counted once, as in k_sweep
                         if (f <= n && (ts < BS - 1 || f == n))
 #pragma unroll

@@ -22,6 +22,7 @@ constexpr int MAXN = 8;
 constexpr int F_NO_LIMITERS = 1;
 constexpr int F_NO_BLEND = 2;
 constexpr int F_FIRST_ORDER = 4;
+constexpr int F_FOUR_EQ = 32;  // the four-equation HRM solved directly (first-order HLLC)
 
 // species table with the derived constants every kernel needs
 struct EosDev {
@@ -608,19 +609,20 @@ __device__ inline void block_max(double* m, double* sh)
 
 // Sec. 4.2 infinite-rate thermal relaxation of one cell (species 0 is the
 // only stiffened gas): A p^2 + B p + C = 0 (eq:Ap_Bp_Cp_1..3), positive root
-// (taken as 2C/(-B - sqrt) when B > 0), T from eq:T_relax_e, then
-// alpha_k = alpha_k rho_k / rho_k(p, T) for k < N-1.  Returns false (and leaves
-// W unchanged) when rho(e - qbar) <= 0 or no positive root exists.
+// (taken as 2C/(-B - sqrt) when B > 0), T from eq:T_relax_e.  relaxed_pT
+// returns p* and T* from W[0 .. N+D] (false when rho(e - qbar) <= 0 or no
+// positive root exists); relax_cell then sets alpha_k = alpha_k rho_k /
+// rho_k(p, T) for k < N-1, and leaves W unchanged where relaxed_pT fails.
 // The root is ill-conditioned in a liquid at low pressure (its condition number
 // grows like gamma_1 pinf_1 / p), so this function evaluates each formula in
 // the order written, with IEEE division and no FMA contraction: its rounding
 // is then reproducible by any plain double-precision evaluation of the same
 // formulas.
 template <int N, int D>
-__device__ inline bool relax_cell(const EosDev& e, double* W)
+__device__ inline bool relaxed_pT(const EosDev& e, const double* W, double& p_out, double& T_out)
 {
 #pragma clang fp contract(off)
-    constexpr int IE = N + D, IA = N + D + 1;
+    constexpr int IE = N + D;
     double rho = 0.0;
 #pragma unroll
     for (int k = 0; k < N; ++k) rho += W[k];
@@ -653,12 +655,107 @@ __device__ inline bool relax_cell(const EosDev& e, double* W)
     const double e_t = re / rho;
     const double T = e_t / (Y0 * (p + e.g[0] * p1) * e.cv[0] / (p + p1) + cvb - Y0 * e.cv[0]);
     if (!(T > 0.0) || !isfinite(T)) return false;
+    p_out = p;
+    T_out = T;
+    return true;
+}
+
+template <int N, int D>
+__device__ inline bool relax_cell(const EosDev& e, double* W)
+{
+#pragma clang fp contract(off)
+    constexpr int IA = N + D + 1;
+    double p, T;
+    if (!relaxed_pT<N, D>(e, W, p, T)) return false;
 #pragma unroll
     for (int k = 0; k < N - 1; ++k) {
         const double rk = (p + e.pinf[k]) / ((e.g[k] - 1.0) * e.cv[k] * T);  // rho_k(p, T)
         W[IA + k] = W[k] / rk;
     }
     return true;
+}
+
+// Sec. 3: pressure and sound speed of the four-equation HRM from
+// alpha_k rho_k, rho u and E.  p is the relaxed p* (eq:p_relax).  c^2 of
+// eq:4_eqn_sos takes Psi_k and Gamma from the implicit derivative of the
+// relaxation quadratic; scaled by rho it reads F(p) = S_v p^2 + B' p + C' with
+//   S_v = sum m_k c_vk,  S_R = sum m_k (c_pk - c_vk),  S_2 = S_R - m_1 (c_p1 - c_v1),
+//   B' = -(re S_R - pinf_1 S_v - pinf_1 m_1 (c_p1 - c_v1)),  C' = -re pinf_1 S_2,
+// re = rho (e - qbar) = sum m_k (e - q_k) and m_k = alpha_k rho_k.  Summing
+// Y_k dF/dm_k and using F(p) = 0 gives sum Y_k Psi_k = (re/rho) X and
+// Gamma = X with X = (S_R p + pinf_1 S_2) / F'(p); and F'(p) = 2 S_v p + B' =
+// S_v p - C'/p.  So
+//   c^2 = p (re + p) (S_R p + pinf_1 S_2) / (rho (S_v p^2 + re pinf_1 S_2)),
+// a quotient of positive terms (no cancellation, unlike 2 A_p p + B_p).
+// p = c = NaN outside the admissible set.
+template <int N, int D>
+__device__ inline void hrm4_pc(const EosDev& e, const St<N, D>& s, double& p, double& c)
+{
+    double w[N + D + 1];
+#pragma unroll
+    for (int k = 0; k < N; ++k) w[k] = s.ar[k];
+#pragma unroll
+    for (int d = 0; d < D; ++d) w[N + d] = s.mom[d];
+    w[N + D] = s.E;
+    double T;
+    if (!relaxed_pT<N, D>(e, w, p, T)) {
+        p = c = __builtin_nan("");
+        return;
+    }
+    double rho = 0.0, Sv = 0.0, SR = 0.0, rq = 0.0, m2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        rho += s.ar[k];
+        Sv += s.ar[k] * e.cv[k];
+        SR += s.ar[k] * (e.cp[k] - e.cv[k]);
+        rq += s.ar[k] * e.q[k];
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) m2 += s.mom[d] * s.mom[d];
+    const double re = s.E - 0.5 * m2 / rho - rq;
+    const double S2 = SR - s.ar[0] * (e.cp[0] - e.cv[0]);
+    const double p1 = e.pinf[0];
+    c = sqrt(p * (re + p) * (SR * p + p1 * S2) / (rho * (Sv * p * p + re * p1 * S2)));
+}
+
+// First-order HLLC for the four-equation HRM solved directly, in direction
+// DIR: the solver of Sec. 4.1.1 on (alpha_k rho_k, rho u, E) with the HRM
+// pressure and sound speed of hrm4_pc, the same wave-speed estimates and
+// sign(0) = 0.  The volume-fraction slots of G are zero.
+template <int N, int D, int DIR>
+__device__ inline void hllc4(const EosDev& e, const St<N, D>& L, const St<N, D>& Rs, double* G)
+{
+    constexpr int IE = N + D, IA = N + D + 1;
+    double pL, cL, pR, cR;
+    hrm4_pc<N, D>(e, L, pL, cL);
+    hrm4_pc<N, D>(e, Rs, pR, cR);
+    const double uL = L.u[DIR], uR = Rs.u[DIR];
+    const double ub = 0.5 * (uL + uR), cb = 0.5 * (cL + cR);
+    const double sL = fmin(ub - cb, uL - cL);
+    const double sR = fmax(ub + cb, uR + cR);
+    const double dL = sL - uL, dR = sR - uR;
+    const double ss = (pR - pL + L.rho * uL * dL - Rs.rho * uR * dR) / (L.rho * dL - Rs.rho * dR);
+    const double sg = ss > 0.0 ? 1.0 : (ss < 0.0 ? -1.0 : 0.0);
+    const double wl = 0.5 * (1.0 + sg), wr = 0.5 * (1.0 - sg);
+    const double sm = fmin(0.0, sL), sp = fmax(0.0, sR);
+    const double chiL = dL / (sL - ss), chiR = dR / (sR - ss);
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        G[k] = wl * (L.ar[k] * uL + sm * (chiL * L.ar[k] - L.ar[k])) +
+               wr * (Rs.ar[k] * uR + sp * (chiR * Rs.ar[k] - Rs.ar[k]));
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const double FLd = L.mom[d] * uL + (d == DIR ? pL : 0.0);
+        const double FRd = Rs.mom[d] * uR + (d == DIR ? pR : 0.0);
+        const double WsL = d == DIR ? chiL * L.rho * ss : chiL * L.rho * L.u[d];
+        const double WsR = d == DIR ? chiR * Rs.rho * ss : chiR * Rs.rho * Rs.u[d];
+        G[N + d] = wl * (FLd + sm * (WsL - L.mom[d])) + wr * (FRd + sp * (WsR - Rs.mom[d]));
+    }
+    const double EsL = chiL * (L.E + (ss - uL) * (L.rho * ss + pL / dL));
+    const double EsR = chiR * (Rs.E + (ss - uR) * (Rs.rho * ss + pR / dR));
+    G[IE] = wl * ((L.E + pL) * uL + sm * (EsL - L.E)) + wr * ((Rs.E + pR) * uR + sp * (EsR - Rs.E));
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) G[IA + k] = 0.0;
 }
 
 }  // namespace hrm

@@ -93,8 +93,9 @@ __device__ inline R sensor_ratio_t(R v0, R v1, R v2, R v3, R v4)
 
 // Output: G = G^{**,-}_{i+1/2} (M slots) and Gp = alpha slots of G^{**,+}.
 // R is the face arithmetic type; node data, the flux limiter and the outputs
-// are double.
-template <int N, int D, int DIR, int NS, int FS, typename R, int WT = 0>
+// are double.  LOW = false leaves out the first-order and direct-HRM branches
+// (selected by flags) for callers that never take them.
+template <int N, int D, int DIR, int NS, int FS, typename R, int WT = 0, bool LOW = true>
 __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, double lam, double* G, double* Gp,
                           unsigned* cnt)
 {
@@ -135,9 +136,15 @@ __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, do
             Glo[IA + k] = Glo[IA + k] - ss * Lr.al[k];
         }
     };
-    if (P.flags & F_FIRST_ORDER) {
+    if (LOW && (P.flags & F_FIRST_ORDER)) {
         St<N, D> L, Rn;
         node_pair(L, Rn);
+        if (P.flags & F_FOUR_EQ) {
+            hllc4<N, D, DIR>(e, L, Rn, G);
+#pragma unroll
+            for (int k = 0; k < N - 1; ++k) Gp[k] = 0.0;
+            return;
+        }
         double Glo[M], Glo_p[NA];
         first_order(L, Rn, Glo, Glo_p);
 #pragma unroll

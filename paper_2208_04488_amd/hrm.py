@@ -25,6 +25,7 @@ FP64, FP32 = 0, 1
 WEIGHTS_IS, WEIGHTS_MLP = 0, 1
 MLP_NPARAM = 1347
 NO_LIMITERS, NO_BLEND, FIRST_ORDER, FUSE_RELAX, NO_GRAPH = 1, 2, 4, 8, 16
+FOUR_EQ = 32  # the four-equation HRM solved directly (first-order HLLC)
 
 
 class hrm_grid(ctypes.Structure):

@@ -15,6 +15,7 @@ from paper_2208_04488_amd import inputs as I
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-11
+SCHEME = 1 | 2 | 4 | 32  # flags both sides understand (limiters, blending, first order, four-equation)
 
 
 @pytest.fixture(scope="module")
@@ -60,10 +61,10 @@ def check_stages(H, orc, prob, W0, flags=0, relax=True, tol=TOL, counters=True, 
     """Three SSP-RK3 stages from the same inputs on both sides."""
     import torch
     N, D = prob.N, prob.D
-    o = orc.from_problem(prob, flags=flags & 7, **(params or {}))
+    o = orc.from_problem(prob, flags=flags & SCHEME, **(params or {}))
     dt, lam = o.dt(W0, prob.cfl)
     cmax = o.max_wavespeed(W0).max()
-    s = solver(H, prob, (flags & 7) | (H.FUSE_RELAX if relax else 0), W=W0, params=params)
+    s = solver(H, prob, (flags & SCHEME) | (H.FUSE_RELAX if relax else 0), W=W0, params=params)
     s.set_slot(dt, lam)
     Wn = s.W.clone()
     Ws = Wn
@@ -96,7 +97,7 @@ def check_stages(H, orc, prob, W0, flags=0, relax=True, tol=TOL, counters=True, 
 
 
 def developed(orc, prob, steps, flags=0):
-    o = orc.from_problem(prob, flags=flags & 7)
+    o = orc.from_problem(prob, flags=flags & SCHEME)
     W = prob.W
     for _ in range(steps):
         W, _ = o.step(W, cfl=prob.cfl, dt_fixed=prob.dt_fixed)
@@ -356,3 +357,43 @@ def test_counters_at_tile_seams(H, orc, maker):
     W0 = developed(orc, prob, 3)
     cnt = check_stages(H, orc, prob, W0)
     assert cnt["alg1"] + cnt["alg2"] + cnt["alg3"] + cnt["alg4"] > 0, cnt
+
+
+# ------------------------------------------------------------------ the four-equation HRM solved directly
+FOUR_EQ_CASES = {
+    "shock_tube": lambda: (I.shock_tube(400), 10),
+    "interface_advection": lambda: (I.interface_advection(500), 20),
+    "config2_small": lambda: (I.config2(128, 64), 2),
+    "config3_ragged": lambda: (I.config3(20), 1),
+}
+
+
+@pytest.mark.parametrize("name", list(FOUR_EQ_CASES))
+def test_four_eq_stage_parity(H, orc, name):
+    """HRM_FOUR_EQ: first-order HLLC of the four-equation model with the HRM
+    pressure and sound speed, then the relaxation (alpha for output)."""
+    prob, steps = FOUR_EQ_CASES[name]()
+    W0 = developed(orc, prob, steps, flags=H.FOUR_EQ)
+    check_stages(H, orc, prob, W0, flags=H.FOUR_EQ)
+
+
+def test_four_eq_stage_parity_without_relaxation(H, orc):
+    """Without the relaxation the volume fractions are not evolved at all."""
+    prob = I.shock_tube(300)
+    W0 = developed(orc, prob, 5, flags=H.FOUR_EQ)
+    check_stages(H, orc, prob, W0, flags=H.FOUR_EQ, relax=False)
+
+
+@pytest.mark.parametrize("maker", ["shock_tube", "config2_small", "config3_small"])
+def test_four_eq_wavespeed_parity(H, orc, maker):
+    """|u| + c with the HRM sound speed (closed form on the device, the
+    implicit derivatives of the relaxation quadratic in the oracle)."""
+    prob = {"shock_tube": lambda: I.shock_tube(400), "config2_small": lambda: I.config2(96, 48),
+            "config3_small": lambda: I.config3(20)}[maker]()
+    W = developed(orc, prob, 3, flags=H.FOUR_EQ)
+    o = orc.from_problem(prob, flags=H.FOUR_EQ)
+    s = solver(H, prob, H.FUSE_RELAX | H.FOUR_EQ, W=W)
+    ms = s.wavespeed()
+    ref = o.max_wavespeed(W)
+    assert np.allclose(ms, ref, rtol=1e-11, atol=0), (ms, ref)
+    s.close()

@@ -38,9 +38,12 @@ extern "C" {
 #define HRM_EADMISSIBLE 4   /* hrm_get_diagnostics: relaxation met states outside script-G */
 #define HRM_EUNSUPPORTED 5  /* (N, dim, precision, weights) combination not built */
 
-/* boundary conditions per side (Sec. 5: extrapolation / periodic) */
+/* boundary conditions per side (Sec. 5: extrapolation / periodic; the
+ * Dirichlet inflow of the Mach-100 water jet, Sec. 5.9).  Periodic sides
+ * come in pairs; a Dirichlet side needs hrm_set_boundary_state. */
 #define HRM_BC_TRANSMISSIVE 0
 #define HRM_BC_PERIODIC 1
+#define HRM_BC_DIRICHLET 2
 
 /* face arithmetic precision; the state, relaxation, limiter bound checks and
  * the accumulation are double in both */
@@ -166,6 +169,21 @@ int hrm_rk_stage(hrm_ctx* ctx, int stage, const double* d_Wn, const double* d_Ws
  * volume-fraction components change.  Cells with rho(e - qbar) <= 0 are left
  * unchanged and counted in hrm_diag.relax_bad. */
 int hrm_relax(hrm_ctx* ctx, double* d_W, void* stream);
+
+/* Dirichlet boundary (Sec. 5.9: the left boundary of the water jet).  The
+ * three ghost nodes beyond side `side` (0 low, 1 high) of dimension `dim` all
+ * take a given state W_b, one per line of cells normal to that face: for the
+ * line through transverse cell (i_a, i_b), a < b the two other dimensions
+ * (i_a, i_b = 0 where a dimension is not used), W_b[c] is
+ * d_state[c * n_a * n_b + i_a + n_a * i_b], c = 0 .. M-1 in the component
+ * order of W.  The states also enter the maximum wavespeed of direction
+ * `dim` (hrm_max_wavespeed, hrm_step).  d_state is device memory of the
+ * caller; it is copied into the context on `stream`, so it may be freed or
+ * changed once that copy has run, and later steps see the new state.  Every
+ * Dirichlet side must be set before the first hrm_rhs / hrm_rk_stage /
+ * hrm_step / hrm_max_wavespeed (HRM_EINVAL otherwise).  HRM_EINVAL if the
+ * side is not Dirichlet or d_state is NULL. */
+int hrm_set_boundary_state(hrm_ctx* ctx, int dim, int side, const double* d_state, void* stream);
 
 /* Learned interpolation weights (an extension; the paper's weights are those
  * of App. C).  On a grid created with weights = HRM_WEIGHTS_MLP every

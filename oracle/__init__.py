@@ -21,7 +21,7 @@ _SRC = os.path.join(_HERE, "hrm_oracle.c")
 _LIB = os.path.join(_HERE, "liborc.so")
 
 MAXN = 8
-TRANSMISSIVE, PERIODIC = 0, 1
+TRANSMISSIVE, PERIODIC, DIRICHLET = 0, 1, 2
 NO_LIMITERS, NO_BLEND, FIRST_ORDER = 1, 2, 4
 FOUR_EQ = 32  # the four-equation HRM solved directly with first-order HLLC
 COUNTERS = ("alg1", "alg2", "interp_hs", "alg3", "alg4", "flux_hs", "relax_bad", "unused")
@@ -61,6 +61,7 @@ class Setup(ctypes.Structure):
         ("Cs", ctypes.c_double), ("qexp", ctypes.c_double), ("psi", ctypes.c_double),
         ("flags", ctypes.c_int),
         ("weights", ctypes.c_int), ("mlp", ctypes.POINTER(ctypes.c_double)),
+        ("bnd", (ctypes.POINTER(ctypes.c_double) * 2) * 3),
     ]
 
 W_IS, W_MLP = 0, 1
@@ -129,11 +130,14 @@ class Oracle:
     """A grid, an EOS table and the paper's parameters, with the oracle's calls.
 
     ``gamma, cv, pinf, q`` list the N species; species 0 is the only one with
-    ``pinf > 0``.  ``bc`` is a list of D pairs (lo, hi) of TRANSMISSIVE/PERIODIC.
+    ``pinf > 0``.  ``bc`` is a list of D pairs (lo, hi) of TRANSMISSIVE,
+    PERIODIC or DIRICHLET; ``boundary`` maps (dim, side) of each Dirichlet
+    side to its ghost states, shape (M, n_a * n_b) with a < b the other two
+    dimensions and index i_a + n_a i_b.
     State arrays are float64 of shape (M, nz, ny, nx), M = 2N + D.
     """
 
-    def __init__(self, N, D, n, dx, bc, gamma, cv, pinf, q, flags=0, mlp=None, **params):
+    def __init__(self, N, D, n, dx, bc, gamma, cv, pinf, q, flags=0, mlp=None, boundary=None, **params):
         s = Setup()
         s.N, s.D = N, D
         nn = list(n) + [1] * (3 - len(n))
@@ -155,6 +159,16 @@ class Oracle:
             self._mlp = _f64(mlp).copy()
             assert self._mlp.size == MLP_NPARAM
             s.weights, s.mlp = W_MLP, _dp(self._mlp)
+        self._bnd = {}
+        for i in range(D):
+            for side in range(2):
+                if (s.bc_lo[i], s.bc_hi[i])[side] != DIRICHLET:
+                    continue
+                a, b = (1, 2) if i == 0 else ((0, 2) if i == 1 else (0, 1))
+                arr = _f64((boundary or {})[(i, side)]).reshape(2 * N + D, -1).copy()
+                assert arr.shape[1] == nn[a] * nn[b]
+                self._bnd[(i, side)] = arr  # referenced by the setup below
+                s.bnd[i][side] = _dp(arr)
         self.s = s
         self.N, self.D, self.M = N, D, 2 * N + D
         self.shape = (self.M, nn[2], nn[1], nn[0])
@@ -337,4 +351,4 @@ def from_problem(prob, flags=0, mlp=None, **params) -> Oracle:
     """An Oracle for a problem description from the input module (plain numbers only)."""
     e = prob.eos
     return Oracle(prob.N, prob.D, prob.n, prob.dx, prob.bc, e.gamma, e.cv, e.pinf, e.q, flags=flags, mlp=mlp,
-                  **params)
+                  boundary=getattr(prob, "boundary", None), **params)

@@ -36,6 +36,7 @@
 
 #define ORC_TRANSMISSIVE 0
 #define ORC_PERIODIC 1
+#define ORC_DIRICHLET 2 /* ghost nodes take a given state per line (Sec. 5.9 inflow) */
 
 #define ORC_NO_LIMITERS 1  /* skip the PP interpolation and flux limiters */
 #define ORC_NO_BLEND 2     /* sigma^s = 0: pure HCS flux (App. B ablation) */
@@ -67,6 +68,7 @@ typedef struct {
     int flags;
     int weights;                      /* ORC_W_IS (App. C) or ORC_W_MLP (learned weights) */
     const double *mlp;                /* ORC_W_MLP: the 1347 network parameters */
+    const double *bnd[3][2];          /* ORC_DIRICHLET sides: ghost states, M x (n_a n_b) */
 } orc_setup;
 
 #define ORC_W_IS 0
@@ -754,6 +756,32 @@ static void load_state(const orc_setup *s, const double *W, long cell, orc_state
     state_from_cons(s, w, st);
 }
 
+/* the two dimensions other than d, in increasing order */
+static void other_dims(int d, int *a, int *b)
+{
+    *a = d == 0 ? 1 : 0;
+    *b = d == 2 ? 1 : 2;
+}
+
+/* node i along dimension d of the line through ijk: a cell, or a ghost node
+ * (index map for transmissive and periodic sides; for a Dirichlet side every
+ * ghost node is the given state of the line) */
+static void load_node(const orc_setup *s, const double *W, int d, int *ijk, int i, orc_state *st)
+{
+    const int side = i < 0 ? 0 : (i >= s->n[d] ? 1 : -1);
+    if (side >= 0 && (side == 0 ? s->bc_lo[d] : s->bc_hi[d]) == ORC_DIRICHLET) {
+        int a, b;
+        other_dims(d, &a, &b);
+        const long nf = (long)s->n[a] * s->n[b], t = ijk[a] + (long)s->n[a] * ijk[b];
+        double w[ORC_MAXM];
+        for (int c = 0; c < NCOMP(s); ++c) w[c] = s->bnd[d][side][(long)c * nf + t];
+        state_from_cons(s, w, st);
+        return;
+    }
+    ijk[d] = map_index(s, d, i);
+    load_state(s, W, cell_index(s, ijk), st);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Semi-discrete right-hand side L(W) (eq:semi_W_G_pm_eqn):                   */
 /*   L_i = - sum_d (G^{**,-}_{i+1/2} - G^{**,+}_{i-1/2}) / dx_d                */
@@ -782,10 +810,7 @@ void orc_rhs(const orc_setup *s, const double *W, const double *lam, double *Lou
                 ijk[o2] = (int)(line / s->n[o1]);
                 /* faces f = -1 .. nd-1 between nodes f and f+1, stored at f+1 */
                 for (int f = -1; f < nd; ++f) {
-                    for (int j = 0; j < 6; ++j) {
-                        ijk[d] = map_index(s, d, f - 2 + j);
-                        load_state(s, W, cell_index(s, ijk), &nodes[j]);
-                    }
+                    for (int j = 0; j < 6; ++j) load_node(s, W, d, ijk, f - 2 + j, &nodes[j]);
                     face_flux(s, d, nodes, lam[d], Gm + (size_t)(f + 1) * M, Gp + (size_t)(f + 1) * M, cnt);
                 }
                 for (int i = 0; i < nd; ++i) {
@@ -1027,6 +1052,28 @@ void orc_max_wavespeed(const orc_setup *s, const double *W, double *out)
             if (v > out[d] || !(v == v)) out[d] = v;
         }
     }
+    /* reading: the Dirichlet ghost states count for the direction normal to their face */
+    for (int d = 0; d < s->D; ++d)
+        for (int side = 0; side < 2; ++side) {
+            if ((side == 0 ? s->bc_lo[d] : s->bc_hi[d]) != ORC_DIRICHLET) continue;
+            int a, b;
+            other_dims(d, &a, &b);
+            const long nf = (long)s->n[a] * s->n[b];
+            for (long t = 0; t < nf; ++t) {
+                double w[ORC_MAXM], c;
+                orc_state st;
+                for (int k = 0; k < NCOMP(s); ++k) w[k] = s->bnd[d][side][(long)k * nf + t];
+                state_from_cons(s, w, &st);
+                c = st.c;
+                if (s->flags & ORC_FOUR_EQ) {
+                    double pTc[3];
+                    hrm_eos(s, st.W, pTc);
+                    c = pTc[2];
+                }
+                const double v = fabs(st.V[IMOM(s, d)]) + c;
+                if (v > out[d] || !(v == v)) out[d] = v;
+            }
+        }
 }
 
 /* Sec. 4.1.2 multi-D time step: tau_d = max(|u_d|+c)/dx_d, dt = CFL/sum tau,

@@ -35,6 +35,8 @@ struct SweepArgs {
     long long ncell;
     int n[3];
     int bclo, bchi;
+    const double* blo;  // Dirichlet ghost states of the low / high face (M x face cells), or null
+    const double* bhi;
     int mode;  // 0: rhs = L_d, 1: rhs += L_d, 2: stage update with rhs + L_d
     int relax;
     double a, b;
@@ -99,12 +101,21 @@ __global__ void __launch_bounds__(BS* BA, SWEEP_WAVES) k_sweep(const SweepArgs A
     for (int q = tid; q < LN * BA; q += BS * BA) {
         const int l = DIR == 0 ? q % LN : q / BA;
         const int a = DIR == 0 ? q / LN : q % BA;
-        const int g = map_bc(c0 - 3 + l, nsw, A.bclo, A.bchi);
+        const int gi = c0 - 3 + l;
         const int ca = min(abase + a, na - 1);
-        const long long cell = g * st[DIR] + ca * st[adim] + other * st[odim];
+        const double* src = A.Ws;
+        long long idx, stride = nc;
+        if ((gi < 0 && A.bclo == BC_DIRICHLET) || (gi >= nsw && A.bchi == BC_DIRICHLET)) {
+            // Dirichlet: every ghost node takes the boundary state of its line
+            src = gi < 0 ? A.blo : A.bhi;
+            idx = ca + (long long)na * other;
+            stride = (long long)na * A.n[odim];
+        } else {
+            idx = map_bc(gi, nsw, A.bclo, A.bchi) * st[DIR] + ca * st[adim] + other * st[odim];
+        }
         double W[M];
 #pragma unroll
-        for (int c = 0; c < M; ++c) W[c] = A.Ws[c * nc + cell];
+        for (int c = 0; c < M; ++c) W[c] = src[c * stride + idx];
         St<N, D> s;
         state_from_W<N, D>(A.e, W, s);
         const int b = base(a, l);
@@ -195,7 +206,10 @@ __global__ void __launch_bounds__(256) k_relax(double* W, long long nc, EosDev e
 }
 
 template <int N, int D>
-__global__ void __launch_bounds__(256) k_wavespeed(const double* W, long long nc, EosDev e, int four, double* part)
+// only >= 0: the other directions' maxima are 0 (Dirichlet ghost states
+// count for the direction normal to their face only)
+__global__ void __launch_bounds__(256) k_wavespeed(const double* W, long long nc, EosDev e, int four, int only,
+                                                    double* part)
 {
     constexpr int M = 2 * N + D;
     __shared__ double sh[4 * 3];
@@ -214,7 +228,8 @@ __global__ void __launch_bounds__(256) k_wavespeed(const double* W, long long nc
             hrm4_pc<N, D>(e, s, p, c);
         }
 #pragma unroll
-        for (int d = 0; d < D; ++d) m[d] = nmax(m[d], fabs(s.u[d]) + c);
+        for (int d = 0; d < D; ++d)
+            if (only < 0 || only == d) m[d] = nmax(m[d], fabs(s.u[d]) + c);
     }
     block_max<D>(m, sh);
     if (threadIdx.x == 0)
@@ -330,6 +345,10 @@ struct hrm_ctx {
     int npart;
     double* d_maxs;
     unsigned long long* d_cnt;
+    double* d_bnd[3][2];     // Dirichlet ghost states per face (M x face cells), null elsewhere
+    int bnd_set[3][2];
+    long long nface[3];      // cells of a face normal to each dimension
+    int nbpart[3];           // wavespeed partial blocks per Dirichlet face of that dimension
     hrm::MlpPacked* d_mlp;  // learned weights (HRM_WEIGHTS_MLP)
     int mlp_ready;
     hipStream_t last_stream;
@@ -424,6 +443,8 @@ struct Ops {
             grd = dim3((c->n[0] + BA - 1) / BA, c->n[1], (c->n[2] + cells - 1) / cells);
         A.bclo = c->bclo[DIR];
         A.bchi = c->bchi[DIR];
+        A.blo = c->d_bnd[DIR][0];
+        A.bhi = c->d_bnd[DIR][1];
         A.idx = 1.0 / c->dx[DIR];
         TimerScope t(c, HRM_T_SWEEP_X + DIR, s);
         if constexpr (D <= 2) {
@@ -458,20 +479,36 @@ struct Ops {
         hipLaunchKernelGGL((hrm::k_relax<N, D>), dim3((unsigned)nb), dim3(256), 0, s, W, c->ncell, c->eos, c->d_cnt);
     }
 
+    // per-block maxima of the cells, then of the Dirichlet ghost states;
+    // returns the number of partial blocks
+    static int wavespeed_parts(hrm_ctx* c, const double* W, hipStream_t s)
+    {
+        const int four = (c->flags & HRM_FOUR_EQ) ? 1 : 0;
+        hipLaunchKernelGGL((hrm::k_wavespeed<N, D>), dim3(c->npart), dim3(256), 0, s, W, c->ncell, c->eos, four, -1,
+                           c->d_part);
+        int nb = c->npart;
+        for (int d = 0; d < D; ++d)
+            for (int side = 0; side < 2; ++side)
+                if (c->d_bnd[d][side]) {
+                    hipLaunchKernelGGL((hrm::k_wavespeed<N, D>), dim3(c->nbpart[d]), dim3(256), 0, s,
+                                       c->d_bnd[d][side], c->nface[d], c->eos, four, d, c->d_part + (size_t)nb * D);
+                    nb += c->nbpart[d];
+                }
+        return nb;
+    }
+
     static void wavespeed_dt(hrm_ctx* c, const double* W, const hrm::DtArgs& a, double* slot, hipStream_t s)
     {
         TimerScope t(c, HRM_T_WAVESPEED, s);
-        hipLaunchKernelGGL((hrm::k_wavespeed<N, D>), dim3(c->npart), dim3(256), 0, s, W, c->ncell, c->eos,
-                           (c->flags & HRM_FOUR_EQ) ? 1 : 0, c->d_part);
-        hipLaunchKernelGGL((hrm::k_reduce_dt<D>), dim3(1), dim3(256), 0, s, c->d_part, c->npart, c->d_maxs, a, slot);
+        const int nb = wavespeed_parts(c, W, s);
+        hipLaunchKernelGGL((hrm::k_reduce_dt<D>), dim3(1), dim3(256), 0, s, c->d_part, nb, c->d_maxs, a, slot);
     }
 
     static void wavespeed(hrm_ctx* c, const double* W, double* out, hipStream_t s)
     {
         TimerScope t(c, HRM_T_WAVESPEED, s);
-        hipLaunchKernelGGL((hrm::k_wavespeed<N, D>), dim3(c->npart), dim3(256), 0, s, W, c->ncell, c->eos,
-                           (c->flags & HRM_FOUR_EQ) ? 1 : 0, c->d_part);
-        hipLaunchKernelGGL((hrm::k_reduce_max<D>), dim3(1), dim3(256), 0, s, c->d_part, c->npart, out);
+        const int nb = wavespeed_parts(c, W, s);
+        hipLaunchKernelGGL((hrm::k_reduce_max<D>), dim3(1), dim3(256), 0, s, c->d_part, nb, out);
     }
 };
 
@@ -501,12 +538,15 @@ hrm::SweepArgs base_args(hrm_ctx* c)
     return A;
 }
 
+int check_boundary(hrm_ctx* c);
+
 // all directions of L(W_s); the last one runs in `final_mode`
 int run_operator(hrm_ctx* c, const double* Ws, const double* Wn, double* Wout, double* rhs, const double* slot,
                  bool stage, double a, double b, int relax, hipStream_t s)
 {
     if (c->weights == HRM_WEIGHTS_MLP && !c->mlp_ready)
         return fail(c, HRM_EINVAL, "learned weights selected but hrm_set_mlp not called%s");
+    if (const int rb = check_boundary(c)) return rb;
     hrm::SweepArgs A = base_args(c);
     A.Ws = Ws;
     A.Wn = Wn;
@@ -529,6 +569,17 @@ int run_operator(hrm_ctx* c, const double* Ws, const double* Wn, double* Wout, d
 
 bool valid_ptr(const void* p) { return p != nullptr; }
 
+// every Dirichlet face has had its state set
+int check_boundary(hrm_ctx* c)
+{
+    for (int d = 0; d < c->D; ++d)
+        for (int side = 0; side < 2; ++side)
+            if (c->d_bnd[d][side] && !c->bnd_set[d][side])
+                return fail(c, HRM_EINVAL, "Dirichlet state of dimension %s%lld not set (hrm_set_boundary_state)", "",
+                            d);
+    return HRM_OK;
+}
+
 hrm::DtArgs dt_args(hrm_ctx* c, double cfl, double dt_fixed, double t_end)
 {
     hrm::DtArgs a;
@@ -546,7 +597,8 @@ int step_enqueue(hrm_ctx* c, double* d_W, double cfl, double dt_fixed, double t_
     static const double RK_A[3] = {0.0, 3.0 / 4.0, 1.0 / 3.0};
     static const double RK_B[3] = {1.0, 1.0 / 4.0, 2.0 / 3.0};
     const hrm::DtArgs a = dt_args(c, cfl, dt_fixed, t_end);
-    int rc = dispatch(c, [&](auto ops) { decltype(ops)::wavespeed_dt(c, d_W, a, d_slot, s); });
+    int rc = check_boundary(c);
+    if (rc == HRM_OK) rc = dispatch(c, [&](auto ops) { decltype(ops)::wavespeed_dt(c, d_W, a, d_slot, s); });
     if (rc == HRM_OK) rc = check_launch(c, "hrm_step wavespeed");
     if (rc == HRM_OK) rc = run_operator(c, d_W, d_W, c->d_W1, c->d_rhs, d_slot, true, RK_A[0], RK_B[0], 1, s);
     if (rc == HRM_OK) rc = run_operator(c, c->d_W1, d_W, c->d_W2, c->d_rhs, d_slot, true, RK_A[1], RK_B[1], 1, s);
@@ -599,7 +651,7 @@ int hrm_create(const hrm_grid* g, const hrm_eos* e, const hrm_params* prm, hrm_c
         if (d < g->dim) {
             for (int side = 0; side < 2; ++side) {
                 const int bc = side ? g->bc_hi[d] : g->bc_lo[d];
-                if (bc != HRM_BC_TRANSMISSIVE && bc != HRM_BC_PERIODIC) return HRM_EINVAL;
+                if (bc != HRM_BC_TRANSMISSIVE && bc != HRM_BC_PERIODIC && bc != HRM_BC_DIRICHLET) return HRM_EINVAL;
             }
             if ((g->bc_lo[d] == HRM_BC_PERIODIC) != (g->bc_hi[d] == HRM_BC_PERIODIC)) return HRM_EINVAL;
         }
@@ -672,11 +724,24 @@ int hrm_create(const hrm_grid* g, const hrm_eos* e, const hrm_params* prm, hrm_c
 
     const size_t bytes = sizeof(double) * (size_t)c->M * (size_t)c->ncell;
     c->npart = (int)std::min<long long>((c->ncell + 255) / 256, 2048);
+    int nparts = c->npart;
+    for (int d = 0; d < 3; ++d) {
+        c->nface[d] = c->ncell / c->n[d];
+        c->nbpart[d] = (int)std::min<long long>((c->nface[d] + 255) / 256, 256);
+        if (d < c->D)
+            for (int side = 0; side < 2; ++side)
+                if ((side ? c->bchi[d] : c->bclo[d]) == HRM_BC_DIRICHLET) nparts += c->nbpart[d];
+    }
     bool ok = true;
+    for (int d = 0; d < c->D; ++d)
+        for (int side = 0; side < 2; ++side)
+            if ((side ? c->bchi[d] : c->bclo[d]) == HRM_BC_DIRICHLET)
+                ok = ok && hipMalloc((void**)&c->d_bnd[d][side], sizeof(double) * (size_t)c->M * c->nface[d]) ==
+                               hipSuccess;
     if (c->D > 1) ok = ok && hipMalloc((void**)&c->d_rhs, bytes) == hipSuccess;
     ok = ok && hipMalloc((void**)&c->d_W1, bytes) == hipSuccess;
     ok = ok && hipMalloc((void**)&c->d_W2, bytes) == hipSuccess;
-    ok = ok && hipMalloc((void**)&c->d_part, sizeof(double) * 3 * (size_t)c->npart) == hipSuccess;
+    ok = ok && hipMalloc((void**)&c->d_part, sizeof(double) * 3 * (size_t)nparts) == hipSuccess;
     ok = ok && hipMalloc((void**)&c->d_maxs, sizeof(double) * 4) == hipSuccess;
     ok = ok && hipMalloc((void**)&c->d_cnt, sizeof(unsigned long long) * 8) == hipSuccess;
     if (c->weights == HRM_WEIGHTS_MLP) ok = ok && hipMalloc((void**)&c->d_mlp, sizeof(hrm::MlpPacked)) == hipSuccess;
@@ -701,6 +766,8 @@ int hrm_destroy(hrm_ctx* c)
             (void)hipEventDestroy(c->pool[i][0]);
             (void)hipEventDestroy(c->pool[i][1]);
         }
+    for (int d = 0; d < 3; ++d)
+        for (int side = 0; side < 2; ++side) (void)hipFree(c->d_bnd[d][side]);
     (void)hipFree(c->d_rhs);
     (void)hipFree(c->d_W1);
     (void)hipFree(c->d_W2);
@@ -718,6 +785,7 @@ int hrm_max_wavespeed(hrm_ctx* c, const double* d_W, double* d_out, void* stream
 {
     if (!c) return HRM_EINVAL;
     if (!valid_ptr(d_W) || !valid_ptr(d_out)) return fail(c, HRM_EINVAL, "hrm_max_wavespeed: NULL pointer%s", "");
+    if (const int rb = check_boundary(c)) return rb;
     hipStream_t s = (hipStream_t)stream;
     c->last_stream = s;
     const int rc = dispatch(c, [&](auto ops) { decltype(ops)::wavespeed(c, d_W, d_out, s); });
@@ -761,6 +829,21 @@ int hrm_rk_stage(hrm_ctx* c, int stage, const double* d_Wn, const double* d_Ws, 
     c->last_stream = s;
     return run_operator(c, d_Ws, d_Wn, d_Wout, c->d_rhs, d_slot, true, RK_A[stage], RK_B[stage],
                         (c->flags & HRM_FUSE_RELAX) ? 1 : 0, s);
+}
+
+int hrm_set_boundary_state(hrm_ctx* c, int dim, int side, const double* d_state, void* stream)
+{
+    if (!c) return HRM_EINVAL;
+    if (dim < 0 || dim >= c->D || side < 0 || side > 1 || !c->d_bnd[dim][side])
+        return fail(c, HRM_EINVAL, "hrm_set_boundary_state: face (dim %s%lld) is not a Dirichlet face", "", dim);
+    if (!valid_ptr(d_state)) return fail(c, HRM_EINVAL, "hrm_set_boundary_state: NULL pointer%s");
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    if (hipMemcpyAsync(c->d_bnd[dim][side], d_state, sizeof(double) * (size_t)c->M * c->nface[dim],
+                       hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return fail(c, HRM_EDEVICE, "hrm_set_boundary_state: copy failed: %s", hipGetErrorString(hipGetLastError()));
+    c->bnd_set[dim][side] = 1;
+    return HRM_OK;
 }
 
 int hrm_relax(hrm_ctx* c, double* d_W, void* stream)

@@ -564,7 +564,10 @@ __device__ inline void flux_limit(const EosDev& e, const ParDev& P, const St<N, 
     }
 }
 
+constexpr int BC_PERIODIC = 1, BC_DIRICHLET = 2;
+
 // ghost index map: transmissive copies the edge cell, periodic wraps
+// (Dirichlet ghosts are read from the boundary-state array instead)
 __device__ inline int map_bc(int g, int n, int lo, int hi)
 {
     if (g < 0) return lo == 1 ? ((g % n) + n) % n : 0;

@@ -20,7 +20,7 @@ HEADER = os.path.join(os.path.dirname(PKG), "include", "hrm.h")
 
 MAX_SPECIES = 8
 HRM_OK, HRM_EINVAL, HRM_ENOMEM, HRM_EDEVICE, HRM_EADMISSIBLE, HRM_EUNSUPPORTED = range(6)
-BC_TRANSMISSIVE, BC_PERIODIC = 0, 1
+BC_TRANSMISSIVE, BC_PERIODIC, BC_DIRICHLET = 0, 1, 2
 FP64, FP32 = 0, 1
 WEIGHTS_IS, WEIGHTS_MLP = 0, 1
 MLP_NPARAM = 1347
@@ -78,6 +78,7 @@ def _load():
     L.hrm_rhs.argtypes = [vp, vp, vp, vp, vp]
     L.hrm_rk_stage.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp]
     L.hrm_relax.argtypes = [vp, vp, vp]
+    L.hrm_set_boundary_state.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp]
     L.hrm_step.argtypes = [vp, vp, dp, dp, dp, vp, vp]
     L.hrm_get_diagnostics.argtypes = [vp, ctypes.POINTER(hrm_diag)]
     L.hrm_reset_diagnostics.argtypes = [vp, vp]
@@ -191,6 +192,10 @@ def hrm_rk_stage(ctx, stage, Wn, Ws, Wout, slot, stream=None):
 
 def hrm_relax(ctx, W, stream=None):
     return _check(ctx, lib.hrm_relax(ctx, _ptr(W), _stream(stream)))
+
+
+def hrm_set_boundary_state(ctx, dim, side, state, stream=None):
+    return _check(ctx, lib.hrm_set_boundary_state(ctx, int(dim), int(side), _ptr(state), _stream(stream)))
 
 
 def hrm_step(ctx, W, cfl, dt_fixed, t_end, slot, stream=None):
@@ -362,6 +367,15 @@ class Solver:
         self.maxs = torch.zeros(4, dtype=torch.float64, device=dev)
         if mlp is not None:
             hrm_set_mlp(self.ctx, mlp)
+        self._bnd = {}
+        for (d, side), Wb in getattr(prob, "boundary", {}).items():
+            self.set_boundary(d, side, Wb)
+
+    def set_boundary(self, d, side, Wb):
+        """Ghost states of a Dirichlet side, shape (M, cells of the face)."""
+        t = self.torch.from_numpy(np.ascontiguousarray(Wb, dtype=np.float64)).to(self.W.device)
+        self._bnd[(d, side)] = t  # kept until the context is gone
+        hrm_set_boundary_state(self.ctx, d, side, t)
 
     def close(self):
         if self.ctx:

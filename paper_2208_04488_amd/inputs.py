@@ -20,7 +20,7 @@ from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
-TRANSMISSIVE, PERIODIC = 0, 1
+TRANSMISSIVE, PERIODIC, DIRICHLET = 0, 1, 2
 TRACE = 1e-8  # volume fraction of an absent species (Sec. 5 initial data)
 
 
@@ -149,6 +149,9 @@ class Problem:
     dt_fixed: float = 0.0
     x0: Tuple[float, ...] = ()  # lower corner of the domain
     meta: dict = field(default_factory=dict)
+    # Dirichlet sides: (dim, side) -> ghost states, shape (M, n_a * n_b), a < b the
+    # other two dimensions, index i_a + n_a * i_b
+    boundary: dict = field(default_factory=dict)
 
     @property
     def N(self) -> int:
@@ -299,6 +302,25 @@ def shock_tube(n=500, extreme=False):
                        t_end=t_end, dt_fixed=dt)
     pr.meta.update(T_left=left[4], T_right=right[4])
     return pr
+
+
+def water_jet(nx=1024, ny=512, L=1.0, u_jet=1.5e5, t_end=6e-6):
+    """Sec. 5.9 Mach-100 water jet: [0, L] x [-L/4, L/4] of air (liquid
+    fraction 1e-8) at 101325 Pa / 298 K, at rest (Table 14).  The left side is
+    a Dirichlet inflow (Table 15): water (air fraction 1e-8) at u = 1.5e5 m/s
+    for |y| <= 0.05 L, the ambient air at rest elsewhere, both at 101325 Pa /
+    298 K; the other sides are transmissive."""
+    eos = table1_eos()
+    dx = (L / nx, 0.5 * L / ny)
+    y = -0.25 * L + (np.arange(ny) + 0.5) * dx[1]
+    air = [np.full((ny, nx), TRACE), np.full((ny, nx), 1.0 - TRACE)]
+    W = equilibrium_state(eos, air, [np.zeros((ny, nx))] * 2, P_ATM, T_ATM)
+    jet = np.abs(y) <= 0.05 * L
+    a1 = np.where(jet, 1.0 - TRACE, TRACE)
+    Wb = equilibrium_state(eos, [a1, 1.0 - a1], [np.where(jet, u_jet, 0.0), np.zeros(ny)], P_ATM, T_ATM)
+    return Problem("water_jet", eos, 2, (nx, ny), dx, [(DIRICHLET, TRANSMISSIVE), (TRANSMISSIVE, TRANSMISSIVE)],
+                   _as4(W, 2), cfl=0.4, t_end=t_end, x0=(0.0, -0.25 * L),
+                   boundary={(0, 0): Wb.reshape(Wb.shape[0], ny)}, meta=dict(u_jet=u_jet))
 
 
 # ----------------------------------------------------------------------------

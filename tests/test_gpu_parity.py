@@ -397,3 +397,76 @@ def test_four_eq_wavespeed_parity(H, orc, maker):
     ref = o.max_wavespeed(W)
     assert np.allclose(ms, ref, rtol=1e-11, atol=0), (ms, ref)
     s.close()
+
+
+# ------------------------------------------------------------------ Dirichlet sides
+def _with_velocity(eos, Wf, d, du):
+    """Face states (M, cells) with velocity component d raised by du."""
+    N = eos.N
+    Wf = Wf.copy()
+    rho = Wf[:N].sum(0)
+    u = Wf[N + d] / rho
+    Wf[N + d] = rho * (u + du)
+    Wf[Wf.shape[0] - N] += 0.5 * rho * ((u + du) ** 2 - u ** 2)  # E sits at index N + D
+    return Wf
+
+
+def dirichlet_problem(kind):
+    if kind == "water_jet":
+        return I.water_jet(128, 64), 5
+    if kind == "config2_inflow_left_and_top":
+        pr = I.config2(100, 37)
+        pr.bc = [(I.DIRICHLET, I.TRANSMISSIVE), (I.TRANSMISSIVE, I.DIRICHLET)]
+        W = pr.W
+        pr.boundary = {(0, 0): _with_velocity(pr.eos, W[:, 0, :, 0], 0, 80.0),
+                       (1, 1): _with_velocity(pr.eos, W[:, 0, -1, :], 1, -30.0)}
+        return pr, 2
+    pr = I.config3(20)  # x-low inflow, face cells indexed y + ny z
+    pr.bc = [(I.DIRICHLET, I.TRANSMISSIVE)] + list(pr.bc[1:])
+    M = pr.M
+    pr.boundary = {(0, 0): _with_velocity(pr.eos, pr.W[:, :, :, 0].reshape(M, -1), 0, 50.0)}
+    return pr, 1
+
+
+@pytest.mark.parametrize("kind", ["water_jet", "config2_inflow_left_and_top", "config3_inflow"])
+def test_dirichlet_stage_parity(H, orc, kind):
+    prob, steps = dirichlet_problem(kind)
+    W0 = developed(orc, prob, steps)
+    check_stages(H, orc, prob, W0)
+
+
+@pytest.mark.parametrize("kind", ["water_jet", "config2_inflow_left_and_top", "config3_inflow"])
+def test_dirichlet_wavespeed_parity(H, orc, kind):
+    """The Dirichlet ghost states count in the wavespeed of their direction."""
+    prob, _ = dirichlet_problem(kind)
+    o = orc.from_problem(prob)
+    s = solver(H, prob, H.FUSE_RELAX)
+    ms = s.wavespeed()
+    assert np.allclose(ms, o.max_wavespeed(prob.W), rtol=1e-13, atol=0)
+    s.close()
+
+
+def test_dirichlet_errors(H):
+    """A Dirichlet side without its state stops every call that reads it;
+    only Dirichlet sides take a state."""
+    import torch
+    prob = I.water_jet(64, 32)
+    g = H.make_grid(prob.D, prob.n, prob.dx, prob.bc, flags=H.FUSE_RELAX)
+    e = prob.eos
+    ctx = H.hrm_create(g, H.make_eos(e.gamma, e.cv, e.pinf, e.q), None)
+    try:
+        W = torch.from_numpy(prob.W).cuda()
+        slot = torch.zeros(8, dtype=torch.float64, device="cuda")
+        with pytest.raises(H.HrmError, match="Dirichlet"):
+            H.hrm_step(ctx, W, 0.4, 0.0, 0.0, slot)
+        with pytest.raises(H.HrmError, match="Dirichlet"):
+            H.hrm_max_wavespeed(ctx, W, slot)
+        Wb = torch.from_numpy(prob.boundary[(0, 0)]).cuda()
+        with pytest.raises(H.HrmError, match="not a Dirichlet face"):
+            H.hrm_set_boundary_state(ctx, 1, 0, Wb)
+        H.hrm_set_boundary_state(ctx, 0, 0, Wb)
+        H.hrm_step(ctx, W, 0.4, 0.0, 0.0, slot)
+        torch.cuda.synchronize()
+        assert torch.isfinite(W).all()
+    finally:
+        H.hrm_destroy(ctx)

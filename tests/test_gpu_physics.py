@@ -146,3 +146,57 @@ def test_gas_liquid_shock_tube_resolution_comparison(H):
         assert 0.9 < fo4[q] / fo5[q] < 1.1
         assert 0.5 < fo4[q] / pp[q] < 2.0
         assert e["hrm_first_order_500"][q] > 2.5 * pp[q]
+
+
+def run_water_jet(H, flags, t_stop=6e-6, max_steps=12000, chunk=200):
+    """Sec. 5.9 at the paper's 1024 x 512 to t_stop (or until the relaxation
+    meets an inadmissible state or the time is no longer finite)."""
+    import torch
+    prob = I.water_jet()
+    s = H.Solver(prob, flags=flags)
+    s.set_slot(0.0, [0.0, 0.0], t=0.0)
+    steps, t = 0, 0.0
+    while steps < max_steps:
+        for _ in range(chunk):
+            s.step(cfl=0.4, t_end=t_stop)
+        steps += chunk
+        torch.cuda.synchronize()
+        t = s.slot[4].item()
+        d = s.diagnostics()
+        if not np.isfinite(t) or d["relax_bad"] > 0 or t >= t_stop * (1 - 1e-12):
+            break
+    W = s.state().reshape(prob.M, prob.n[1], prob.n[0])
+    s.close()
+    return prob, W, t, steps, d
+
+
+def test_water_jet_at_full_size(H):
+    """Sec. 5.9: with the positivity-preserving limiters the Mach-100 jet runs
+    to 6 us at 1024 x 512 with every state admissible; the water that entered
+    through the Dirichlet side is the inflow rho u times the jet width and the
+    time; the jet has crossed most of the domain."""
+    prob, W, t, steps, d = run_water_jet(H, H.FUSE_RELAX)
+    print(f"limiters on: t = {t:.4g} s after {steps} steps, counters {d}")
+    assert t == pytest.approx(6e-6, rel=1e-12) and d["relax_bad"] == 0
+    N = 2
+    a1 = W[N + 2 + 1]  # alpha_1 sits at N + D + 1
+    assert np.isfinite(W).all() and (W[:N] >= 0).all() and (a1 >= 0).all() and (a1 <= 1).all()
+    dx, dy = prob.dx
+    Wb = prob.boundary[(0, 0)]
+    jet = Wb[2] > 0
+    inflow = float((Wb[0, jet] * prob.meta["u_jet"]).sum() * dy * t)
+    water = float(W[0].sum() * dx * dy)
+    print(f"water mass {water:.5g} kg/m, inflow {inflow:.5g} kg/m")
+    assert water == pytest.approx(inflow, rel=0.02)
+    x = prob.centres(0)
+    centre = a1[prob.n[1] // 2]
+    tip = x[centre > 0.5].max()
+    print(f"jet tip (alpha_1 > 0.5 on the axis) at x = {tip:.3f} m")
+    assert 0.5 < tip < 1.0
+
+
+def test_water_jet_fails_without_limiters(H):
+    """Sec. 5.9: with the limiters off the same run meets inadmissible states."""
+    prob, W, t, steps, d = run_water_jet(H, H.FUSE_RELAX | H.NO_LIMITERS)
+    print(f"limiters off: stopped at t = {t:.4g} s after {steps} steps, counters {d}")
+    assert d["relax_bad"] > 0 or not np.isfinite(t) or not np.isfinite(W).all()

@@ -359,6 +359,95 @@ def config5(nx=2048, ny=1024):
                    meta=dict(x_split=0.7, left=left[:4], right=right[:4]))
 
 
+def stiffened_hugoniot(gamma, pinf, rho0, p0, p1):
+    """Shock from a stiffened gas at rest (rho0, p0) to the pressure p1: the
+    Hugoniot density ratio with p shifted by pinf,
+    rho1/rho0 = ((g+1)(p1+pinf) + (g-1)(p0+pinf)) / ((g-1)(p1+pinf) + (g+1)(p0+pinf)),
+    then mass and momentum balance: u1 = sqrt((p1 - p0)(1/rho0 - 1/rho1)) and
+    the shock speed s = rho1 u1 / (rho1 - rho0).  Returns (rho1, u1, s)."""
+    a, b = p1 + pinf, p0 + pinf
+    rho1 = rho0 * ((gamma + 1.0) * a + (gamma - 1.0) * b) / ((gamma - 1.0) * a + (gamma + 1.0) * b)
+    u1 = math.sqrt((p1 - p0) * (1.0 / rho0 - 1.0 / rho1))
+    return rho1, u1, rho1 * u1 / (rho1 - rho0)
+
+
+def shock_interface(n=1600):
+    """Sec. 5.6: 1D extreme shock-interface interaction on [0, 1] m (reading:
+    the domain length is not printed).  Water (air and SF6 traces 1e-8 each)
+    at 101325 Pa / 298 K, a 1e12 Pa shock at x = 0.15 (post-shock state from
+    the stiffened-gas Hugoniot of the water, T from its EOS, traces at that p
+    and T), a half air / half SF6 mixture (water trace 1e-8) beyond 0.3;
+    transmissive; t = 1.26e-5 s; the paper's step 3e-9 s at 1600 points."""
+    eos = table1_eos("SF6")
+    x = (np.arange(n) + 0.5) / n
+    rho_w0 = species_density(eos, 0, P_ATM, T_ATM)
+    rho_w1, u1, _ = stiffened_hugoniot(eos.gamma[0], eos.pinf[0], rho_w0, P_ATM, 1e12)
+    T1 = species_temperature(eos, 0, 1e12, rho_w1)
+    post, water, gas = x < 0.15, (x >= 0.15) & (x < 0.3), x >= 0.3
+    a1 = np.where(gas, TRACE, 1.0 - 2 * TRACE)
+    a2 = np.where(gas, 0.5 - 0.5 * TRACE, TRACE)
+    alpha = [a1, a2, 1.0 - a1 - a2]
+    p = np.where(post, 1e12, P_ATM)
+    T = np.where(post, T1, T_ATM)
+    W = equilibrium_state(eos, alpha, [np.where(post, u1, 0.0)], p, T)
+    return Problem("shock_interface", eos, 1, (n,), (1.0 / n,), [(TRANSMISSIVE, TRANSMISSIVE)], _as4(W, 1),
+                   t_end=1.26e-5, dt_fixed=3e-9 * 1600 / n, x0=(0.0,), meta=dict(T_post=T1, u_post=u1))
+
+
+def bubble_collapse(nx=2048, ny=1280, L=1e-3):
+    """Sec. 5.8: a 1.9 GPa shock in water hits an air cylinder.  [0, 24L] x
+    [-7.5L, 7.5L], L = 1 mm; the cylinder (radius 3L, centre (12L, 0)) and the
+    pre-shock water at 101325 Pa / 298 K (Table 13); the plane shock at
+    x = 6.6L with post-shock water from the stiffened-gas Hugoniot (T from the
+    EOS, air trace at that p and T); interfaces sharp at the cell centres;
+    transmissive.  meta["t0"] is the (negative) time of the initial state so
+    that t = 0 when the shock reaches the cylinder."""
+    eos = table1_eos()
+    dx = (24 * L / nx, 15 * L / ny)
+    x = (np.arange(nx) + 0.5) * dx[0]
+    y = -7.5 * L + (np.arange(ny) + 0.5) * dx[1]
+    X, Y = np.meshgrid(x, y)
+    rho_w0 = species_density(eos, 0, P_ATM, T_ATM)
+    rho_w1, u1, s = stiffened_hugoniot(eos.gamma[0], eos.pinf[0], rho_w0, P_ATM, 1.9e9)
+    T1 = species_temperature(eos, 0, 1.9e9, rho_w1)
+    post = X < 6.6 * L
+    air = (X - 12 * L) ** 2 + Y ** 2 < (3 * L) ** 2
+    a1 = np.where(air, TRACE, 1.0 - TRACE)
+    p = np.where(post, 1.9e9, P_ATM)
+    T = np.where(post, T1, T_ATM)
+    W = equilibrium_state(eos, [a1, 1.0 - a1], [np.where(post, u1, 0.0), np.zeros_like(X)], p, T)
+    return Problem("bubble_collapse", eos, 2, (nx, ny), dx, [(TRANSMISSIVE, TRANSMISSIVE)] * 2, _as4(W, 2),
+                   cfl=0.4, x0=(0.0, -7.5 * L),
+                   meta=dict(t0=-2.4 * L / s, u_post=u1, shock_speed=s, T_post=T1, R_b=3 * L, centre=(12 * L, 0.0)))
+
+
+def undex(nx=1536, ny=1920, L=1.0):
+    """Sec. 5.10: three-species extreme underwater explosion.  Water below
+    y = 0, air above, a detonation-product bubble (ideal gas gamma 1.25,
+    c_p 1000) of radius 0.3L at (0, -0.5L) at 1e12 Pa and 1250 kg/m^3 (T from
+    its EOS); the rest at 101325 Pa / 298 K; traces 1e-8 (Table 16); at rest;
+    transmissive; t = 0.25 ms.  Reading: the domain is [-8L, 8L] x [-6L, 14L]
+    (16L x 20L with the surface 6L above the bottom, as the figure of the set-up
+    shows; the printed y-range [0, 20L] would put the bubble outside it).
+    Interfaces sharp at the cell centres."""
+    eos = table1_eos("detonation")
+    dx = (16 * L / nx, 20 * L / ny)
+    x = -8 * L + (np.arange(nx) + 0.5) * dx[0]
+    y = -6 * L + (np.arange(ny) + 0.5) * dx[1]
+    X, Y = np.meshgrid(x, y)
+    gas = X ** 2 + (Y + 0.5 * L) ** 2 < (0.3 * L) ** 2
+    water = (Y < 0) & ~gas
+    air = (Y >= 0) & ~gas
+    a1 = np.where(water, 1.0 - 2 * TRACE, TRACE)
+    a2 = np.where(air, 1.0 - 2 * TRACE, TRACE)
+    T3 = species_temperature(eos, 2, 1e12, 1250.0)
+    p = np.where(gas, 1e12, P_ATM)
+    T = np.where(gas, T3, T_ATM)
+    W = equilibrium_state(eos, [a1, a2, 1.0 - a1 - a2], [np.zeros_like(X)] * 2, p, T)
+    return Problem("undex", eos, 2, (nx, ny), dx, [(TRANSMISSIVE, TRANSMISSIVE)] * 2, _as4(W, 2), cfl=0.4,
+                   t_end=0.25e-3, x0=(-8 * L, -6 * L), meta=dict(T_gas=T3))
+
+
 def rankine_hugoniot_ideal(gamma, R, p0, T0, mach):
     """Post-shock state of a normal shock of Mach number `mach` moving into an
     ideal gas at rest; returns (p1, rho1, u1, T1)."""

@@ -1,0 +1,212 @@
+"""Robustness problems of the paper at its own sizes on the GPU.
+
+Sec. 5.5 (1D extreme gas/liquid shock tube, 1e12 | 1e5 Pa), Sec. 5.6 (1D
+three-species extreme shock-interface interaction), Sec. 5.8 (2D 1.9 GPa
+shock / air-bubble collapse at 2048 x 1280) and Sec. 5.10 (2D three-species
+underwater explosion at 1536 x 1920, 1e12 Pa): with the positivity-preserving
+limiters every state stays admissible; with them off the paper reports
+failures, and so must this library (detected by the relaxation's admissibility
+counter or non-finite values, never by a fault: the kernels index nothing by
+state values).  Where the paper gives a number (the jet impact time of
+Sec. 5.8) or a converged reference, the runs are checked against it.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2208_04488_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2208_04488_amd import hrm
+    return hrm
+
+
+def device_admissible(s):
+    """Every partial density >= 0 and every volume fraction in [0, 1], all
+    finite (checked on the device with torch reductions)."""
+    import torch
+    N, D = s.prob.N, s.prob.D
+    W = s.W
+    a = W[N + D + 1:]
+    aN = 1.0 - a.sum(0)
+    ok = torch.isfinite(W).all() & (W[:N] >= 0).all() & (a >= 0).all() & (aN >= 0).all()
+    return bool(ok.item())
+
+
+def advance(H, s, t_stop, dt_fixed=0.0, chunk=200, max_steps=2_000_000):
+    """Steps to t_stop in chunks; after each chunk it stops early at an
+    inadmissible state (relaxation counter or the state itself), a time that
+    is no longer finite, or after max_steps.  Returns (t, steps, counters);
+    counters["admissible"] says whether the last state checked was."""
+    import torch
+    steps = 0
+    while True:
+        for _ in range(chunk):
+            s.step(cfl=0.4, dt_fixed=dt_fixed, t_end=t_stop)
+        steps += chunk
+        torch.cuda.synchronize()
+        t = s.slot[4].item()
+        d = s.diagnostics()
+        d["admissible"] = device_admissible(s)
+        if (not math.isfinite(t) or d["relax_bad"] > 0 or not d["admissible"] or t >= t_stop * (1 - 1e-12)
+                or steps >= max_steps):
+            return t, steps, d
+
+
+def failed(t, d):
+    return d["relax_bad"] > 0 or not d["admissible"] or not math.isfinite(t)
+
+
+def admissible(W, N, D):
+    a = W[N + D + 1:]
+    aN = 1.0 - a.sum(0)
+    return bool(np.isfinite(W).all() and (W[:N] >= 0).all() and (a >= 0).all() and (aN >= 0).all())
+
+
+# ------------------------------------------------------------------ Sec. 5.5
+def extreme_shock_tube_l1(H, n, dt, flags, chunk=500):
+    from oracle import exact_riemann as ER
+    prob = I.shock_tube(n, extreme=True)
+    s = H.Solver(prob, flags=flags)
+    s.set_slot(0.0, [0.0], t=0.0)
+    t, steps, d = advance(H, s, 1e-5, dt_fixed=dt, chunk=chunk)
+    W = s.state().reshape(prob.M, -1)
+    s.close()
+    eos = prob.eos
+    L = dict(rho=1000.0, u=0.0, p=1e12, gamma=eos.gamma[0], pinf=eos.pinf[0])
+    R = dict(rho=20.0, u=0.0, p=1e5, gamma=eos.gamma[1], pinf=0.0)
+    rex, uex, pex = ER.solve(prob.centres(0), t, 0.8, L, R)
+    l1 = float(np.abs(W[0] + W[1] - rex).sum() * prob.dx[0]) if np.isfinite(W).all() else math.inf
+    return l1, W, t, d
+
+
+def test_extreme_shock_tube(H):
+    """PP-WCNS-IS at 1000 points (dt 8e-9 s) stays admissible and is about as
+    accurate as first-order HLLC at 10000 points (dt 8e-10 s), fractional or
+    the HRM solved directly; without the limiters it fails."""
+    R = H.FUSE_RELAX
+    pp, W, t, d = extreme_shock_tube_l1(H, 1000, 8e-9, R)
+    assert t == pytest.approx(1e-5, rel=1e-12) and d["relax_bad"] == 0 and admissible(W, 2, 1)
+    fo5, W5, _, d5 = extreme_shock_tube_l1(H, 10000, 8e-10, R | H.FIRST_ORDER)
+    fo4, W4, _, d4 = extreme_shock_tube_l1(H, 10000, 8e-10, R | H.FOUR_EQ)
+    print(f"L1(rho) vs exact: PP-WCNS-IS 1000 {pp:.4g}; first order 10000: fractional {fo5:.4g}, HRM {fo4:.4g}")
+    assert d5["relax_bad"] == 0 and admissible(W5, 2, 1)
+    assert pp < 2.0 * min(fo5, fo4)
+    off, Woff, toff, doff = extreme_shock_tube_l1(H, 1000, 8e-9, R | H.NO_LIMITERS, chunk=5)
+    print(f"limiters off: stopped at t = {toff:.4g}, counters {doff}")
+    assert failed(toff, doff)
+
+
+# ------------------------------------------------------------------ Sec. 5.6
+def run_shock_interface(H, n, dt, flags):
+    prob = I.shock_interface(n)
+    s = H.Solver(prob, flags=flags)
+    s.set_slot(0.0, [0.0], t=0.0)
+    t, steps, d = advance(H, s, prob.t_end, dt_fixed=dt, chunk=2000 if n > 20000 else 500)
+    W = s.state().reshape(prob.M, -1)
+    s.close()
+    return prob, W, t, d
+
+
+def _restrict(ref, n):
+    """Cell averages of a fine 1D field on n coarse cells."""
+    return ref.reshape(n, -1).mean(axis=1)
+
+
+def test_extreme_shock_interface(H):
+    """Three species at 1e12 Pa: admissible with the limiters at 800 and 1600
+    points, converging to the paper's reference (first-order HLLC, 200000
+    points, dt 2.4e-11 s); without the limiters it fails."""
+    R = H.FUSE_RELAX
+    _, Wref, tref, dref = run_shock_interface(H, 200000, 2.4e-11, R | H.FIRST_ORDER)
+    assert dref["relax_bad"] == 0 and admissible(Wref, 3, 1)
+    errs = {}
+    for n, dt in ((800, 6e-9), (1600, 3e-9)):
+        prob, W, t, d = run_shock_interface(H, n, dt, R)
+        assert t == pytest.approx(1.26e-5, rel=1e-12) and d["relax_bad"] == 0 and admissible(W, 3, 1)
+        errs[n] = [float(np.abs(W[k] - _restrict(Wref[k], n)).sum() / n) for k in range(3)]
+    prob, W, t, d = run_shock_interface(H, 10000, 4.8e-10, R | H.FIRST_ORDER)
+    errs["fo10000"] = [float(np.abs(W[k] - _restrict(Wref[k], 10000)).sum() / 10000) for k in range(3)]
+    print("L1 of the partial densities against the 200000-point reference:", errs)
+    for k in range(3):
+        assert errs[1600][k] < errs[800][k]
+    off = run_shock_interface(H, 1600, 3e-9, R | H.NO_LIMITERS)
+    print(f"limiters off: stopped at t = {off[2]:.4g}, counters {off[3]}")
+    assert failed(off[2], off[3])
+
+
+# ------------------------------------------------------------------ Sec. 5.8
+def test_bubble_collapse_jet_impact(H):
+    """At 2048 x 1280 the water jet reaches the far bubble wall at about
+    2.80 us after the shock meets the bubble (the paper's value), the cavity
+    shrinks monotonically from 1 us on, and every state stays admissible."""
+    import torch
+    prob = I.bubble_collapse()
+    s = H.Solver(prob, flags=H.FUSE_RELAX)
+    t0 = prob.meta["t0"]
+    s.set_slot(0.0, [0.0, 0.0], t=t0)
+    ny = prob.n[1]
+    dA = prob.dx[0] * prob.dx[1]
+    V0 = math.pi * prob.meta["R_b"] ** 2
+    N, D = 2, 2
+    ia = N + D + 1
+    hist, impact = [], None
+    t = t0
+    for k in range(1, 161):
+        t_next = k * 0.025e-6
+        t, steps, d = advance(H, s, t_next, chunk=25)
+        assert d["relax_bad"] == 0 and d["admissible"], (t, d)
+        air = 1.0 - s.W[ia, 0]
+        V = float(air.sum().item()) * dA / V0
+        axis = float(air[ny // 2 - 1: ny // 2 + 1].max().item())
+        hist.append((t, V, axis))
+        if impact is None and t > 1.0e-6 and axis < 0.5:
+            impact = t
+            break
+    W = s.state().reshape(prob.M, ny, prob.n[0])
+    s.close()
+    for tt, V, ax in hist[::8]:
+        print(f"t = {tt * 1e6:6.3f} us: V/V0 = {V:.4f}, max air fraction on the axis = {ax:.3f}")
+    print(f"jet impact at t = {impact * 1e6 if impact else float('nan'):.3f} us (paper: 2.80 us)")
+    assert admissible(W, N, D)
+    assert impact is not None and impact == pytest.approx(2.80e-6, rel=0.05)
+    V = [v for tt, v, _ in hist if tt >= 1.0e-6]
+    assert all(b <= a + 1e-3 for a, b in zip(V, V[1:])) and V[-1] < 0.5 * V[0]
+
+
+# ------------------------------------------------------------------ Sec. 5.10
+def test_undex(H):
+    """1536 x 1920, three species, 1e12 Pa: admissible to 0.25 ms with the
+    limiters, and the species masses and the total energy are those of the
+    initial state (no wave has reached the transmissive sides, where the
+    ambient state is at rest, so no mass or energy crosses them); without the
+    limiters it fails."""
+    prob = I.undex()
+    N, D = 3, 2
+    dA = prob.dx[0] * prob.dx[1]
+    W0 = prob.W.reshape(prob.M, -1)
+    m0 = [float(W0[k].sum() * dA) for k in range(N)] + [float(W0[N + D].sum() * dA)]
+    s = H.Solver(prob, flags=H.FUSE_RELAX)
+    s.set_slot(0.0, [0.0, 0.0], t=0.0)
+    t, steps, d = advance(H, s, prob.t_end, chunk=200)
+    W = s.state().reshape(prob.M, -1)
+    s.close()
+    print(f"limiters on: t = {t:.4g} s after {steps} steps, counters {d}")
+    assert t == pytest.approx(0.25e-3, rel=1e-12) and d["relax_bad"] == 0 and admissible(W, N, D)
+    m1 = [float(W[k].sum() * dA) for k in range(N)] + [float(W[N + D].sum() * dA)]
+    for a, b in zip(m0, m1):
+        assert b == pytest.approx(a, rel=1e-10)
+    s = H.Solver(prob, flags=H.FUSE_RELAX | H.NO_LIMITERS)
+    s.set_slot(0.0, [0.0, 0.0], t=0.0)
+    t, steps, d = advance(H, s, prob.t_end, chunk=50, max_steps=1000)
+    W = s.state()
+    s.close()
+    print(f"limiters off: stopped at t = {t:.4g} s after {steps} steps, counters {d}")
+    assert failed(t, d)

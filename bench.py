@@ -32,7 +32,11 @@ def node_flops(N, D):
 def face_flops(N, D):
     """Algorithmic FP64 operations of one midpoint (add, sub, mul, div, sqrt,
     tanh count one each; comparisons, min/max and |x| count zero; limiter
-    branches that fire only on bad faces count zero).  Breakdown in the design doc."""
+    branches that fire only on bad faces count zero): two HLLC solves, the
+    projection set-up and the characteristic values of six nodes, 2M WENO-IS
+    interpolations of 105 each, the back-projection, the always-executed part
+    of the interpolation limiter, two face states, the HCS flux and the
+    sensor, each counted by hand from the formulas."""
     M = 2 * N + D
     return 253 * M + 141 * N + 56 * D + 251
 
@@ -345,8 +349,8 @@ def main():
                     help="only run a plain 512 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (DESIGN.md describes how it "
-              "would shard). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (a sharded run would split the "
+              "grid into slabs and exchange 3-cell halos every stage). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

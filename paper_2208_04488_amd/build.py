@@ -18,7 +18,7 @@ SOURCES = ["hrm.hip", "hrm_batch.hip", "hrm_mlp.hip"]
 SOURCE_FLAGS = {"hrm_batch.hip": ["-mllvm", "-disable-machine-licm"]}
 ARCH = "gfx950"
 
-# -packed-fp32-ops: no v_pk_*_f32 from the compiler
+# -packed-fp32-ops: the compiler emits no packed FP32 (v_pk_*_f32) instructions
 HIPFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -328,6 +328,14 @@ int hrm_batch_run(hrm_batch* b, double* d_W, int nsteps, double cfl, void* strea
  * creation) to h_t[nprob]. */
 int hrm_batch_time(hrm_batch* b, double* h_t);
 
+/* Per-problem end times, h_tend[nprob] on the host (copied after the work
+ * already enqueued on the batch has finished).  A problem's step is clipped
+ * so that its time does not pass its end time (as hrm_compute_dt clips with
+ * t_end), and a problem at its end time takes no further steps, so a run of
+ * enough steps brings every problem exactly to its own end time.  Values
+ * <= 0 mean no end time (the default).  HRM_EINVAL for a NaN. */
+int hrm_batch_set_end_times(hrm_batch* b, const double* h_tend);
+
 /* Synchronise and copy the counters (as hrm_get_diagnostics; counts every
  * face of every problem once per stage). */
 int hrm_batch_get_diagnostics(hrm_batch* b, hrm_diag* out);

@@ -30,6 +30,7 @@ struct BatchArgs {
     const double* dx;
     const int* order;      // processing order (longest first)
     double* t;             // per-problem time
+    const double* tend;    // per-problem end time (<= 0: none)
     int* queue;
     unsigned long long* cnt;
     long long T;
@@ -66,7 +67,7 @@ __global__ void __launch_bounds__(BS, 3) k_batch(const BatchArgs A)
     static_assert(BS % 64 == 0 && BS <= 256, "block size");
     __shared__ double lds[F::COUNT * FS];
     __shared__ double sh[12];
-    __shared__ double sdt[2];
+    __shared__ double sdt[3];
     __shared__ int spid;
     const int ts = threadIdx.x;
     const long long T = A.T;
@@ -97,14 +98,21 @@ __global__ void __launch_bounds__(BS, 3) k_batch(const BatchArgs A)
             }
             block_max<1>(m, sh);
             if (ts == 0) {
+                // the step is clipped so that t does not pass the problem's
+                // end time (as hrm_compute_dt does); a problem that has
+                // reached it takes no further steps
                 const double tau = m[0] / dxb;
-                const double dt = A.cfl / tau;
+                const double t = A.t[b], te = A.tend[b];
+                double dt = A.cfl / tau;
+                if (te > 0.0 && t + dt > te) dt = fmax(te - t, 0.0);
                 sdt[0] = dt;
                 sdt[1] = dt / ((tau / tau) * dxb);
-                A.t[b] += dt;
+                sdt[2] = te > 0.0 && t >= te ? 1.0 : 0.0;
+                if (sdt[2] == 0.0) A.t[b] = te > 0.0 && t + dt >= te ? te : t + dt;
             }
             __syncthreads();
             const double dt = uniform(sdt[0]), lam = uniform(sdt[1]);
+            if (uniform(sdt[2]) != 0.0) break;
 
             for (int stage = 0; stage < 3; ++stage) {
                 const double* Ws = stage == 0 ? A.W : (stage == 1 ? A.W1 : A.W2);
@@ -182,6 +190,7 @@ struct hrm_batch {
     double* d_dx;
     int* d_order;
     double* d_t;
+    double* d_tend;
     int* d_queue;
     unsigned long long* d_cnt;
     int threads, blocks, ksteps;
@@ -233,6 +242,7 @@ int enqueue_chunk(hrm_batch* b, double* d_W, double cfl, hipStream_t s)
     A.dx = b->d_dx;
     A.order = b->d_order;
     A.t = b->d_t;
+    A.tend = b->d_tend;
     A.queue = b->d_queue;
     A.cnt = b->d_cnt;
     A.T = b->T;
@@ -351,12 +361,14 @@ int hrm_batch_create(const hrm_eos* e, const hrm_params* prm, int nprob, const l
     ok = ok && hipMalloc((void**)&b->d_dx, sizeof(double) * nprob) == hipSuccess;
     ok = ok && hipMalloc((void**)&b->d_order, sizeof(int) * nprob) == hipSuccess;
     ok = ok && hipMalloc((void**)&b->d_t, sizeof(double) * nprob) == hipSuccess;
+    ok = ok && hipMalloc((void**)&b->d_tend, sizeof(double) * nprob) == hipSuccess;
     ok = ok && hipMalloc((void**)&b->d_queue, sizeof(int)) == hipSuccess;
     ok = ok && hipMalloc((void**)&b->d_cnt, sizeof(unsigned long long) * 8) == hipSuccess;
     ok = ok && hipMemcpy(b->d_off, h_offsets, sizeof(long long) * (nprob + 1), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(b->d_dx, h_dx, sizeof(double) * nprob, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(b->d_order, order.data(), sizeof(int) * nprob, hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemset(b->d_t, 0, sizeof(double) * nprob) == hipSuccess;
+    ok = ok && hipMemset(b->d_tend, 0, sizeof(double) * nprob) == hipSuccess;
     ok = ok && hipMemset(b->d_cnt, 0, sizeof(unsigned long long) * 8) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
@@ -379,6 +391,7 @@ int hrm_batch_destroy(hrm_batch* b)
     (void)hipFree(b->d_dx);
     (void)hipFree(b->d_order);
     (void)hipFree(b->d_t);
+    (void)hipFree(b->d_tend);
     (void)hipFree(b->d_queue);
     (void)hipFree(b->d_cnt);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
@@ -437,6 +450,18 @@ int hrm_batch_time(hrm_batch* b, double* h_t)
     if (hipStreamSynchronize(b->last_stream) != hipSuccess ||
         hipMemcpy(h_t, b->d_t, sizeof(double) * b->nprob, hipMemcpyDeviceToHost) != hipSuccess)
         return bfail(b, HRM_EDEVICE, "hrm_batch_time: copy failed");
+    return HRM_OK;
+}
+
+int hrm_batch_set_end_times(hrm_batch* b, const double* h_tend)
+{
+    if (!b || !h_tend) return HRM_EINVAL;
+    for (int i = 0; i < b->nprob; ++i)
+        if (!(h_tend[i] == h_tend[i])) return bfail(b, HRM_EINVAL, "hrm_batch_set_end_times: NaN end time");
+    // ordered after the work already enqueued on the batch
+    if (hipStreamSynchronize(b->last_stream) != hipSuccess ||
+        hipMemcpy(b->d_tend, h_tend, sizeof(double) * b->nprob, hipMemcpyHostToDevice) != hipSuccess)
+        return bfail(b, HRM_EDEVICE, "hrm_batch_set_end_times: copy failed");
     return HRM_OK;
 }
 

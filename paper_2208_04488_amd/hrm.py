@@ -93,6 +93,7 @@ def _load():
     L.hrm_batch_configure.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     L.hrm_batch_run.argtypes = [vp, vp, ctypes.c_int, dp, vp]
     L.hrm_batch_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.hrm_batch_set_end_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.hrm_batch_get_diagnostics.argtypes = [vp, ctypes.POINTER(hrm_diag)]
     fp = ctypes.POINTER(ctypes.c_float)
     ll = ctypes.c_longlong
@@ -316,6 +317,11 @@ def hrm_batch_time(b, nprob) -> np.ndarray:
     return t
 
 
+def hrm_batch_set_end_times(b, tend):
+    t = np.ascontiguousarray(tend, dtype=np.float64)
+    return _bcheck(b, lib.hrm_batch_set_end_times(b, t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+
 def hrm_batch_get_diagnostics(b) -> dict:
     d = hrm_diag()
     rc = lib.hrm_batch_get_diagnostics(b, ctypes.byref(d))
@@ -452,6 +458,9 @@ class BatchSolver:
 
     def times(self) -> np.ndarray:
         return hrm_batch_time(self.b, self.batch.nprob)
+
+    def set_end_times(self, tend):
+        hrm_batch_set_end_times(self.b, tend)
 
     def diagnostics(self):
         return hrm_batch_get_diagnostics(self.b)

@@ -210,3 +210,49 @@ def test_undex(H):
     s.close()
     print(f"limiters off: stopped at t = {t:.4g} s after {steps} steps, counters {d}")
     assert failed(t, d)
+
+
+# ------------------------------------------------------------------ the same problems in one batch
+def batch_of(problems):
+    """1D problems of one species table back to back as one ragged batch."""
+    Ws = [p.W.reshape(p.M, -1) for p in problems]
+    offsets = np.concatenate([[0], np.cumsum([w.shape[1] for w in Ws])]).astype(np.int64)
+    return I.Batch("robustness", problems[0].eos, np.ascontiguousarray(np.concatenate(Ws, axis=1)), offsets,
+                   np.array([p.dx[0] for p in problems]), cfl=0.4)
+
+
+@pytest.mark.parametrize("species", [2, 3])
+def test_extreme_problems_in_one_batch(H, species):
+    """Secs. 5.4 and 5.5 (two species) or Sec. 5.6 at two resolutions (three
+    species) as one persistent batch, each problem to its own end time at CFL
+    0.4: every problem lands exactly on its end time, stays admissible, and
+    equals the single-grid solver run the same way, bit for bit."""
+    if species == 2:
+        probs = [I.shock_tube(1000, extreme=True), I.shock_tube(500), I.shock_tube(1200), I.shock_tube(600, True)]
+    else:
+        probs = [I.shock_interface(800), I.shock_interface(1600)]
+    batch = batch_of(probs)
+    tend = np.array([p.t_end for p in probs])
+    bs = H.BatchSolver(batch)
+    bs.set_end_times(tend)
+    for _ in range(100):
+        bs.run(200)
+        t = bs.times()
+        if np.all(t >= tend):
+            break
+    W = bs.state()
+    d = bs.diagnostics()
+    bs.close()
+    assert np.array_equal(t, tend), (t, tend)
+    assert d["relax_bad"] == 0
+    off = batch.offsets
+    for b, p in enumerate(probs):
+        Wb = W[:, off[b]:off[b + 1]]
+        assert admissible(Wb, p.N, 1), (b, p.name)
+        s = H.Solver(p, flags=H.FUSE_RELAX)
+        s.set_slot(0.0, [0.0], t=0.0)
+        ts, steps, ds = advance(H, s, p.t_end, chunk=1)
+        Ws = s.state().reshape(p.M, -1)
+        s.close()
+        assert ts == p.t_end
+        assert np.array_equal(Wb, Ws), (b, p.name, np.abs(Wb - Ws).max())

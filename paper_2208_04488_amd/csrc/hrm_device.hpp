@@ -575,15 +575,20 @@ __device__ inline int map_bc(int g, int n, int lo, int hi)
     return g;
 }
 
-// sum each counter over the wave, one atomic per non-zero counter
+// sum each counter over the wave, one atomic per non-zero counter.  Most
+// counters are zero on every lane of most waves: a ballot skips those (the
+// branch is wave-uniform), and the others are summed in 32 bits (a lane's
+// counts stay far below 2^26 per launch) by lane permutes.
 __device__ inline void flush_counters(const unsigned* c, unsigned long long* dst)
 {
+    const int lane = __lane_id();
 #pragma unroll
     for (int k = 0; k < C_N; ++k) {
-        unsigned long long v = c[k];
+        if (__ballot(c[k] != 0u) == 0ull) continue;
+        int v = (int)c[k];
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (__lane_id() == 0 && v != 0ull) atomicAdd(&dst[k], v);
+        for (int off = 32; off > 0; off >>= 1) v += __builtin_amdgcn_ds_bpermute((lane ^ off) << 2, v);
+        if (lane == 0) atomicAdd(&dst[k], (unsigned long long)(unsigned)v);
     }
 }
 

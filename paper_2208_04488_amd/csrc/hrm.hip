@@ -237,6 +237,24 @@ __global__ void __launch_bounds__(256) k_wavespeed(const double* W, long long nc
         for (int d = 0; d < D; ++d) part[blockIdx.x * D + d] = m[d];
 }
 
+// this thread's share of the maximum of nb partials (one block of 256
+// threads): eight loads in flight per pass instead of one
+template <int D>
+__device__ inline void partial_max(const double* part, int nb, double* m)
+{
+    for (int i0 = threadIdx.x; i0 < nb; i0 += 256 * 8) {
+        double v[8][D];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int d = 0; d < D; ++d) v[u][d] = i0 + 256 * u < nb ? part[(i0 + 256 * u) * D + d] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int d = 0; d < D; ++d) m[d] = nmax(m[d], v[u][d]);
+    }
+}
+
 template <int D>
 __global__ void __launch_bounds__(256) k_reduce_max(const double* part, int nb, double* out)
 {
@@ -244,9 +262,7 @@ __global__ void __launch_bounds__(256) k_reduce_max(const double* part, int nb, 
     double m[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) m[d] = 0.0;
-    for (int i = threadIdx.x; i < nb; i += 256)
-#pragma unroll
-        for (int d = 0; d < D; ++d) m[d] = nmax(m[d], part[i * D + d]);
+    partial_max<D>(part, nb, m);
     block_max<D>(m, sh);
     if (threadIdx.x == 0)
 #pragma unroll
@@ -289,9 +305,7 @@ __global__ void __launch_bounds__(256) k_reduce_dt(const double* part, int nb, d
     double m[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) m[d] = 0.0;
-    for (int i = threadIdx.x; i < nb; i += 256)
-#pragma unroll
-        for (int d = 0; d < D; ++d) m[d] = nmax(m[d], part[i * D + d]);
+    partial_max<D>(part, nb, m);
     block_max<D>(m, sh);
     if (threadIdx.x == 0) {
 #pragma unroll

@@ -88,6 +88,8 @@ __device__ inline R sensor_ratio_t(R v0, R v1, R v2, R v3, R v4)
 {
     const R num = fabs(-v0 + (R)16 * v1 - (R)30 * v2 + (R)16 * v3 - v4);
     const R den = fabs(v0 + (R)16 * v1 + (R)30 * v2 + (R)16 * v3 + v4);
+    if constexpr (sizeof(R) == sizeof(double))
+        if (den > 1e-290) return num * rcp_newton(den);  // densities and pressures: far from subnormal
     return den > (R)0 ? num / den : (num > (R)0 ? (R)1 : (R)0);
 }
 
@@ -159,7 +161,14 @@ __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, do
 #pragma unroll
     for (int k = 0; k < N; ++k) arb[k] = (R)0.5 * (nv(2, k) + nv(3, k));
     const R rb = (R)0.5 * (nv(2, F::RHO) + nv(3, F::RHO)), cb = (R)0.5 * (nv(2, F::C) + nv(3, F::C));
-    const R irc = (R)1 / (rb * cb), irc2 = irc / cb;
+    // 1/(rho c), 1/(rho c^2) = rho (1/(rho c))^2 and 1/(2c) = rho/(2 rho c) from one
+    // reciprocal (the means of two admissible nodes are positive)
+    R irc;
+    if constexpr (sizeof(R) == sizeof(double))
+        irc = rcp_newton(rb * cb);
+    else
+        irc = (R)1 / (rb * cb);
+    const R irc2 = irc * irc * rb;
     const double eps = P.eps_weno;
     R UL[M], UR[M], v[6];
 #pragma unroll
@@ -195,7 +204,7 @@ __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, do
 
     // back to primitive slots: V = R U
     St<N, D, R> VL, VR;
-    const R h2c = (R)0.5 / cb, hrc = (R)0.5 * rb * cb;
+    const R h2c = (R)0.5 * rb * irc, hrc = (R)0.5 * rb * cb;
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
         const R* U = side ? UR : UL;
@@ -250,8 +259,17 @@ __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, do
                                  sensor_ratio_t<double>(pr[0], pr[1], pr[2], pr[3], pr[4]));
         const double z = sr * sp;
         const double arg = P.Cs * (P.qexp == 2.0 ? z * z : pow(z, P.qexp));
-        // tanh is exactly 0 at 0 and rounds to 1 for arguments >= 22
-        sig = (R)(arg == 0.0 ? 0.0 : (arg >= 22.0 ? 1.0 : tanh(arg)));
+        // tanh is exactly 0 at 0 and rounds to 1 for arguments >= 22; below
+        // 0.01 (smooth flow: nearly every face) its odd series to x^7 is
+        // exact to double rounding (the next term is below 3e-18 x)
+        double th;
+        if (arg < 0.01) {
+            const double a2 = arg * arg;
+            th = arg * (1.0 + a2 * (-1.0 / 3.0 + a2 * (2.0 / 15.0 - a2 * (17.0 / 315.0))));
+        } else {
+            th = arg >= 22.0 ? 1.0 : tanh(arg);
+        }
+        sig = (R)th;
     }
 
     // HCS reconstruction (eq:reconstructed_G, eq:reconstructed_vel) and blending.

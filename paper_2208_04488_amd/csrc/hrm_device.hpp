@@ -98,6 +98,18 @@ __device__ inline void mixture(const EosDev& e, const R* al, R& Gam, R& Pi)
     }
 }
 
+// 1/x from the hardware reciprocal refined by two Newton steps: within about
+// an ulp of the IEEE quotient, in 5 instructions instead of the ~10 of an
+// IEEE division.  x must be a normal number (not 0, infinite, NaN or
+// subnormal), as the WENO-IS weight sums and the densities and mixture
+// Gamma of cells are; elsewhere the IEEE quotient is kept.
+__device__ inline double rcp_newton(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return fma(fma(-x, r, 1.0), r, r);
+}
+
 // conservative W[M] -> full state (hot-path step a1)
 template <int N, int D>
 __device__ inline void state_from_W(const EosDev& e, const double* W, St<N, D>& s)
@@ -117,7 +129,7 @@ __device__ inline void state_from_W(const EosDev& e, const double* W, St<N, D>& 
         asum += W[IA + k];
     }
     s.al[N - 1] = 1.0 - asum;
-    const double irho = 1.0 / rho;
+    const double irho = rcp_newton(rho);
     double m2 = 0.0;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -127,7 +139,7 @@ __device__ inline void state_from_W(const EosDev& e, const double* W, St<N, D>& 
     }
     double Gam, Pi;
     mixture<N>(e, s.al, Gam, Pi);
-    const double iG = 1.0 / Gam;
+    const double iG = rcp_newton(Gam);
     s.E = W[IE];
     const double re = W[IE] - 0.5 * m2 * irho - rq;
     s.p = (re - Pi) * iG;
@@ -180,23 +192,32 @@ __device__ inline double rhoe_tilde(const EosDev& e, const double* W)
     return W[N + D] - 0.5 * m2 / rho - rq;
 }
 
-// 1/x from the hardware reciprocal refined by two Newton steps: within about
-// an ulp of the IEEE quotient, in 5 instructions instead of the ~10 of an
-// IEEE division.  x must be a positive normal number, as the WENO-IS weight
-// sums are (every term is positive and far from the double range limits).
-__device__ inline double rcp_newton(double x)
-{
-    double r = __builtin_amdgcn_rcp(x);
-    r = fma(fma(-x, r, 1.0), r, r);
-    return fma(fma(-x, r, 1.0), r, r);
-}
-
 // App. C incremental-stencil WENO, left-biased at i+1/2 from u_{i-2..i+2}.
 // The four unnormalised weights are scaled by the common product of the
 // denominators so the weighting needs one reciprocal instead of six divisions.  The
 // product spans up to ~1e-75..1e55 for the ranges met here, which double
 // holds; in the FP32 variant the candidates and smoothness indicators are
 // float and only this weighting is done in double.
+template <typename R>
+__device__ inline R weno_is_weigh(R s0, R s1, R s2, R s3, R q0, R q1, R q01, R q2, R q3, R qt, double eps)
+{
+    // weights (double): eta_k times Q = B0 B1 B01 B2 B3, B = beta + eps
+    const double B0 = (double)q0 + eps, B1 = (double)q1 + eps, B01 = (double)q01 + eps;
+    const double B2 = (double)q2 + eps, B3 = (double)q3 + eps, tau = qt;
+    const double t2 = tau * tau;
+    const double B23 = B2 * B3, B0B1 = B0 * B1;
+    const double e0 = (15.0 / 32.0) * (B0 * B01 + t2) * B1 * B23;
+    const double e1 = (5.0 / 32.0) * (B1 * B01 + t2) * B0 * B23;
+    const double e2 = (5.0 / 16.0) * (B2 + tau) * B0B1 * B01 * B3;
+    const double e3 = (1.0 / 16.0) * (B3 + tau) * B0B1 * B01 * B2;
+    if constexpr (sizeof(R) == sizeof(double)) {
+        return (e0 * s0 + e1 * s1 + e2 * s2 + e3 * s3) * rcp_newton(e0 + e1 + e2 + e3);
+    } else {
+        const double inv = rcp_newton(e0 + e1 + e2 + e3);
+        return (R)(e0 * inv) * s0 + (R)(e1 * inv) * s1 + (R)(e2 * inv) * s2 + (R)(e3 * inv) * s3;
+    }
+}
+
 template <typename R>
 __device__ inline R weno_is(R um2, R um1, R u0, R up1, R up2, double eps)
 {
@@ -216,20 +237,53 @@ __device__ inline R weno_is(R um2, R um1, R u0, R up1, R up2, double eps)
     const R q2 = c13 * b2a * b2a + (R)0.25 * b2b * b2b;
     const R q3 = c13 * b3a * b3a + (R)0.25 * b3b * b3b;
     const R qt = c13 * t5a * t5a + (R)0.25 * t5b * t5b;
-    // weights (double): eta_k times Q = B0 B1 B01 B2 B3, B = beta + eps
-    const double B0 = (double)q0 + eps, B1 = (double)q1 + eps, B01 = (double)q01 + eps;
-    const double B2 = (double)q2 + eps, B3 = (double)q3 + eps, tau = qt;
-    const double t2 = tau * tau;
-    const double B23 = B2 * B3, B0B1 = B0 * B1;
-    const double e0 = (15.0 / 32.0) * (B0 * B01 + t2) * B1 * B23;
-    const double e1 = (5.0 / 32.0) * (B1 * B01 + t2) * B0 * B23;
-    const double e2 = (5.0 / 16.0) * (B2 + tau) * B0B1 * B01 * B3;
-    const double e3 = (1.0 / 16.0) * (B3 + tau) * B0B1 * B01 * B2;
-    if constexpr (sizeof(R) == sizeof(double)) {
-        return (e0 * s0 + e1 * s1 + e2 * s2 + e3 * s3) * rcp_newton(e0 + e1 + e2 + e3);
-    } else {
-        const double inv = rcp_newton(e0 + e1 + e2 + e3);
-        return (R)(e0 * inv) * s0 + (R)(e1 * inv) * s1 + (R)(e2 * inv) * s2 + (R)(e3 * inv) * s3;
+    return weno_is_weigh<R>(s0, s1, s2, s3, q0, q1, q01, q2, q3, qt, eps);
+}
+
+// Both biased values at i+1/2 from v[0..5] = u_{i-2..i+3}: the left-biased
+// weno_is(v0..v4) and the right-biased weno_is of the mirrored stencil
+// v5..v1.  The two share the candidate (u_i + u_{i+1})/2, beta_0 and the
+// squared second differences about i and i+1 (beta_01 of one side has the
+// second-difference term of beta_2 of the other), which are formed once.
+template <typename R>
+__device__ inline void weno_is_pair(const R* v, double eps, R& l, R& r)
+{
+    constexpr R c13 = (R)(13.0 / 12.0);
+    const R s0 = (R)0.5 * (v[2] + v[3]);
+    const R a0 = v[2] - v[3];
+    const R q0 = a0 * a0;
+    const R dA = v[1] - (R)2 * v[2] + v[3];  // second difference about i
+    const R dB = v[2] - (R)2 * v[3] + v[4];  // second difference about i+1
+    const R cA = c13 * dA * dA, cB = c13 * dB * dB;
+    {
+        const R s1 = (R)0.5 * ((R)3 * v[2] - v[1]);
+        const R s2 = (R)0.125 * ((R)3 * v[2] + (R)6 * v[3] - v[4]);
+        const R s3 = (R)0.125 * ((R)3 * v[0] - (R)10 * v[1] + (R)15 * v[2]);
+        const R a1 = v[1] - v[2], b01b = v[1] - v[3], b2b = (R)3 * v[2] - (R)4 * v[3] + v[4];
+        const R b3a = v[0] - (R)2 * v[1] + v[2], b3b = v[0] - (R)4 * v[1] + (R)3 * v[2];
+        const R t5a = v[4] - (R)4 * v[3] + (R)6 * v[2] - (R)4 * v[1] + v[0];
+        const R t5b = v[4] - (R)2 * v[3] + (R)2 * v[1] - v[0];
+        const R q1 = a1 * a1;
+        const R q01 = cA + (R)0.25 * b01b * b01b;
+        const R q2 = cB + (R)0.25 * b2b * b2b;
+        const R q3 = c13 * b3a * b3a + (R)0.25 * b3b * b3b;
+        const R qt = c13 * t5a * t5a + (R)0.25 * t5b * t5b;
+        l = weno_is_weigh<R>(s0, s1, s2, s3, q0, q1, q01, q2, q3, qt, eps);
+    }
+    {
+        const R s1 = (R)0.5 * ((R)3 * v[3] - v[4]);
+        const R s2 = (R)0.125 * ((R)3 * v[3] + (R)6 * v[2] - v[1]);
+        const R s3 = (R)0.125 * ((R)3 * v[5] - (R)10 * v[4] + (R)15 * v[3]);
+        const R a1 = v[4] - v[3], b01b = v[4] - v[2], b2b = (R)3 * v[3] - (R)4 * v[2] + v[1];
+        const R b3a = v[5] - (R)2 * v[4] + v[3], b3b = v[5] - (R)4 * v[4] + (R)3 * v[3];
+        const R t5a = v[1] - (R)4 * v[2] + (R)6 * v[3] - (R)4 * v[4] + v[5];
+        const R t5b = v[1] - (R)2 * v[2] + (R)2 * v[4] - v[5];
+        const R q1 = a1 * a1;
+        const R q01 = cB + (R)0.25 * b01b * b01b;
+        const R q2 = cA + (R)0.25 * b2b * b2b;
+        const R q3 = c13 * b3a * b3a + (R)0.25 * b3b * b3b;
+        const R qt = c13 * t5a * t5a + (R)0.25 * t5b * t5b;
+        r = weno_is_weigh<R>(s0, s1, s2, s3, q0, q1, q01, q2, q3, qt, eps);
     }
 }
 

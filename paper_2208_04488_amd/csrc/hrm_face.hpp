@@ -56,8 +56,7 @@ __device__ inline void load_node(const double* nd, int j, St<N, D>& s)
 template <typename R>
 __device__ inline void weno_pair(const R* v, double eps, R& l, R& r)
 {
-    l = weno_is<R>(v[0], v[1], v[2], v[3], v[4], eps);
-    r = weno_is<R>(v[5], v[4], v[3], v[2], v[1], eps);
+    weno_is_pair<R>(v, eps, l, r);
 }
 
 // the pair of interpolated values at i+1/2 from v[0..5] = nodes i-2..i+3:

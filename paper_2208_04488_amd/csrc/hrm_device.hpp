@@ -442,43 +442,51 @@ template <int N, int D, int DIR>
 __device__ inline bool flux_limit_clean(const EosDev& e, const ParDev& P, const St<N, D>& L, const St<N, D>& R,
                                         double lam, const double* Gho, const double* Gho_p)
 {
-    constexpr int M = 2 * N + D, IE = N + D, IA = N + D + 1;
+    constexpr int IE = N + D, IA = N + D + 1;
     if (!P.fast_flux_limiter) return false;
+    // the half-cell states W+ (from node i) and W- (from node i+1) are formed
+    // slot by slot and checked at once, with running sums for rho, rho q-bar,
+    // |rho u|^2 and the volume fractions, instead of being held whole
     const double uL = L.u[DIR], uR = R.u[DIR];
     const double l2 = 2.0 * lam;
-    double Wp[M], Wm[M];
+    bool ok = true;
+    double rp = 0.0, rm = 0.0, qp = 0.0, qm = 0.0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        Wp[k] = L.ar[k] - l2 * (Gho[k] - L.ar[k] * uL);
-        Wm[k] = R.ar[k] + l2 * (Gho[k] - R.ar[k] * uR);
+        const double wp = L.ar[k] - l2 * (Gho[k] - L.ar[k] * uL);
+        const double wm = R.ar[k] + l2 * (Gho[k] - R.ar[k] * uR);
+        ok = ok && wp >= P.eps_f_ar && wm >= P.eps_f_ar && isfinite(Gho[k]) && isfinite(wp) && isfinite(wm);
+        rp += wp;
+        rm += wm;
+        qp += wp * e.q[k];
+        qm += wm * e.q[k];
     }
+    double m2p = 0.0, m2m = 0.0;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-        Wp[N + d] = L.mom[d] - l2 * (Gho[N + d] - (L.mom[d] * uL + (d == DIR ? L.p : 0.0)));
-        Wm[N + d] = R.mom[d] + l2 * (Gho[N + d] - (R.mom[d] * uR + (d == DIR ? R.p : 0.0)));
+        const double wp = L.mom[d] - l2 * (Gho[N + d] - (L.mom[d] * uL + (d == DIR ? L.p : 0.0)));
+        const double wm = R.mom[d] + l2 * (Gho[N + d] - (R.mom[d] * uR + (d == DIR ? R.p : 0.0)));
+        ok = ok && isfinite(Gho[N + d]) && isfinite(wp) && isfinite(wm);
+        m2p += wp * wp;
+        m2m += wm * wm;
     }
-    Wp[IE] = L.E - l2 * (Gho[IE] - (L.E + L.p) * uL);
-    Wm[IE] = R.E + l2 * (Gho[IE] - (R.E + R.p) * uR);
+    const double Ep = L.E - l2 * (Gho[IE] - (L.E + L.p) * uL);
+    const double Em = R.E + l2 * (Gho[IE] - (R.E + R.p) * uR);
+    ok = ok && isfinite(Gho[IE]) && isfinite(Ep) && isfinite(Em);
+    double sp = 0.0, sm = 0.0;
 #pragma unroll
     for (int k = 0; k < N - 1; ++k) {
-        Wp[IA + k] = L.al[k] - l2 * (Gho[IA + k] - 0.0);
-        Wm[IA + k] = R.al[k] + l2 * (Gho_p[k] - 0.0);
+        const double ap = L.al[k] - l2 * (Gho[IA + k] - 0.0);
+        const double am = R.al[k] + l2 * (Gho_p[k] - 0.0);
+        ok = ok && ap >= P.eps_f_a && am >= P.eps_f_a && isfinite(Gho[IA + k]) && isfinite(Gho_p[k]) &&
+             isfinite(ap) && isfinite(am);
+        sp += ap;
+        sm += am;
     }
-    bool ok = true;
-#pragma unroll
-    for (int k = 0; k < N; ++k) ok = ok && Wp[k] >= P.eps_f_ar && Wm[k] >= P.eps_f_ar;
-    double ap[N], am[N];
-    alphas<N, D>(Wp, ap);
-    alphas<N, D>(Wm, am);
-#pragma unroll
-    for (int k = 0; k < N; ++k) ok = ok && ap[k] >= P.eps_f_a && am[k] >= P.eps_f_a;
-    const double rep = rhoe_tilde<N, D>(e, Wp), rem = rhoe_tilde<N, D>(e, Wm);
-    ok = ok && rep >= P.eps_f_re && rem >= P.eps_f_re && isfinite(rep) && isfinite(rem);
-#pragma unroll
-    for (int c = 0; c < M; ++c) ok = ok && isfinite(Gho[c]) && isfinite(Wp[c]) && isfinite(Wm[c]);
-#pragma unroll
-    for (int k = 0; k < N - 1; ++k) ok = ok && isfinite(Gho_p[k]);
-    return ok;
+    ok = ok && 1.0 - sp >= P.eps_f_a && 1.0 - sm >= P.eps_f_a;
+    // rho (e - qbar) of each half-cell state, as rhoe_tilde forms it
+    const double rep = Ep - 0.5 * m2p / rp - qp, rem = Em - 0.5 * m2m / rm - qm;
+    return ok && rep >= P.eps_f_re && rem >= P.eps_f_re && isfinite(rep) && isfinite(rem);
 }
 
 template <int N, int D, int DIR>

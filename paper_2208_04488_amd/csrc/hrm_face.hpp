@@ -169,61 +169,51 @@ __device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, do
         irc = (R)1 / (rb * cb);
     const R irc2 = irc * irc * rb;
     const double eps = P.eps_weno;
-    R UL[M], UR[M], v[6];
+    // The characteristic fields are interpolated one at a time and each is
+    // taken back to its primitive slot (V = R U) at once, so that only the
+    // two acoustic fields stay live across the others.
+    St<N, D, R> VL, VR;
+    const R h2c = (R)0.5 * rb * irc, hrc = (R)0.5 * rb * cb;
+    R v[6], aL0, aR0, aLM, aRM;
 #pragma unroll
     for (int j = 0; j < 6; ++j) v[j] = dv(j, F::U + DIR) - dv(j, F::P) * irc;
-    interp_pair<R, WT>(v, eps, P.mlp, UL[0], UR[0]);
+    interp_pair<R, WT>(v, eps, P.mlp, aL0, aR0);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) v[j] = dv(j, F::U + DIR) + dv(j, F::P) * irc;
+    interp_pair<R, WT>(v, eps, P.mlp, aLM, aRM);
+    const R dUL = aLM - aL0, dUR = aRM - aR0;
+    VL.u[DIR] = back(F::U + DIR, (R)0.5 * (aL0 + aLM));
+    VR.u[DIR] = back(F::U + DIR, (R)0.5 * (aR0 + aRM));
+    VL.p = back(F::P, hrc * dUL);
+    VR.p = back(F::P, hrc * dUR);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         const R s = arb[k] * irc2;
 #pragma unroll
         for (int j = 0; j < 6; ++j) v[j] = dv(j, k) - s * dv(j, F::P);
-        interp_pair<R, WT>(v, eps, P.mlp, UL[1 + k], UR[1 + k]);
+        R l, r;
+        interp_pair<R, WT>(v, eps, P.mlp, l, r);
+        VL.ar[k] = back(k, l + arb[k] * h2c * dUL);
+        VR.ar[k] = back(k, r + arb[k] * h2c * dUR);
     }
-    {
-        int t = 0;
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            if (d == DIR) continue;
+    for (int d = 0; d < D; ++d) {
+        if (d == DIR) continue;
 #pragma unroll
-            for (int j = 0; j < 6; ++j) v[j] = dv(j, F::U + d);
-            interp_pair<R, WT>(v, eps, P.mlp, UL[1 + N + t], UR[1 + N + t]);
-            ++t;
-        }
+        for (int j = 0; j < 6; ++j) v[j] = dv(j, F::U + d);
+        R l, r;
+        interp_pair<R, WT>(v, eps, P.mlp, l, r);
+        VL.u[d] = back(F::U + d, l);
+        VR.u[d] = back(F::U + d, r);
     }
 #pragma unroll
     for (int k = 0; k < N - 1; ++k) {
 #pragma unroll
         for (int j = 0; j < 6; ++j) v[j] = dv(j, IA + k);
-        interp_pair<R, WT>(v, eps, P.mlp, UL[N + D + k], UR[N + D + k]);
-    }
-#pragma unroll
-    for (int j = 0; j < 6; ++j) v[j] = dv(j, F::U + DIR) + dv(j, F::P) * irc;
-    interp_pair<R, WT>(v, eps, P.mlp, UL[M - 1], UR[M - 1]);
-
-    // back to primitive slots: V = R U
-    St<N, D, R> VL, VR;
-    const R h2c = (R)0.5 * rb * irc, hrc = (R)0.5 * rb * cb;
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-        const R* U = side ? UR : UL;
-        St<N, D, R>& V = side ? VR : VL;
-        const R dU = U[M - 1] - U[0];
-#pragma unroll
-        for (int k = 0; k < N; ++k) V.ar[k] = back(k, U[1 + k] + arb[k] * h2c * dU);
-        int t = 0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            if (d == DIR) {
-                V.u[d] = back(F::U + d, (R)0.5 * (U[0] + U[M - 1]));
-            } else {
-                V.u[d] = back(F::U + d, U[1 + N + t]);
-                ++t;
-            }
-        }
-        V.p = back(F::P, hrc * dU);
-#pragma unroll
-        for (int k = 0; k < N - 1; ++k) V.al[k] = back_d(IA + k, U[N + D + k]);
+        R l, r;
+        interp_pair<R, WT>(v, eps, P.mlp, l, r);
+        VL.al[k] = back_d(IA + k, l);
+        VR.al[k] = back_d(IA + k, r);
     }
 
     // Sec. 4.3.2 interpolation limiter: left against node i, right against node i+1

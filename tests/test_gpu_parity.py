@@ -470,3 +470,50 @@ def test_dirichlet_errors(H):
         assert torch.isfinite(W).all()
     finally:
         H.hrm_destroy(ctx)
+
+
+@pytest.mark.parametrize("name", ["shock_tube", "config2_small"])
+def test_four_eq_fp32_grid_is_the_fp64_solver(H, orc, name):
+    """The direct HRM flux is double at either precision: a grid created with
+    FP32 face arithmetic gives the FP64 grid's stages bit for bit."""
+    import torch
+    prob, steps = FOUR_EQ_CASES[name]()
+    W0 = developed(orc, prob, steps, flags=H.FOUR_EQ)
+    o = orc.from_problem(prob, flags=H.FOUR_EQ)
+    dt, lam = o.dt(W0, prob.cfl)
+    outs = []
+    for precision in (H.FP64, H.FP32):
+        s = H.Solver(prob, flags=H.FOUR_EQ | H.FUSE_RELAX, precision=precision, W=W0)
+        s.set_slot(dt, lam)
+        Wn = s.W.clone()
+        W1 = s.stage(0, Wn, Wn)
+        W2 = s.stage(1, Wn, W1)
+        torch.cuda.synchronize()
+        outs.append((W1.cpu().numpy(), W2.cpu().numpy()))
+        s.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_dirichlet_fp32_steps_track_fp64(H, orc):
+    """Dirichlet ghost states reach the FP32 face arithmetic the same way:
+    ten FP32 steps of the water jet stay admissible and within the FP32
+    bound used for the extreme shock tube (relative L1 of the density
+    1e-4) of the FP64 steps."""
+    import torch
+    prob = I.water_jet(128, 64)
+    outs = []
+    for precision in (H.FP64, H.FP32):
+        s = H.Solver(prob, flags=H.FUSE_RELAX, precision=precision)
+        s.set_slot(0.0, [0.0, 0.0])
+        for _ in range(10):
+            s.step(cfl=0.4)
+        torch.cuda.synchronize()
+        outs.append((s.state(), s.diagnostics()))
+        s.close()
+    (a, da), (b, db) = outs
+    assert da["relax_bad"] == 0 and db["relax_bad"] == 0
+    N, D = prob.N, prob.D
+    ab = b[N + D + 1:]
+    assert np.isfinite(b).all() and (b[:N] >= 0).all() and (ab >= 0).all() and (ab <= 1).all()
+    ra, rb = a[:N].sum(0), b[:N].sum(0)
+    assert np.abs(rb - ra).sum() / np.abs(ra).sum() <= 1e-4

@@ -34,6 +34,18 @@ namespace hrm {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
+// ReLU of 8 accumulator entries, rounded to bfloat16.  The max with 0 is
+// taken on the float bit patterns as 32-bit integers (a float with the sign
+// bit set is a negative integer, -0 included): one integer max per entry,
+// where a float max would first canonicalise its matrix-core operand.
+__device__ inline bf16x8 relu_bf16(const f32x16& acc, int base)
+{
+    bf16x8 b;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) b[q] = (__bf16)__int_as_float(max(__float_as_int(acc[base + q]), 0));
+    return b;
+}
+
 constexpr int MLP_NPARAM = 1347;
 constexpr int MLP_OFF_W1 = 0, MLP_OFF_B1 = 160, MLP_OFF_W2 = 192, MLP_OFF_B2 = 1216, MLP_OFF_W3 = 1248,
               MLP_OFF_B3 = 1344;
@@ -67,21 +79,13 @@ __device__ inline void mlp_block(const MlpPacked* __restrict__ m, const bf16x8 x
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(m->A1[lane], xin, acc, 0, 0, 0);
-    bf16x8 p0, p1;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        p0[q] = (__bf16)fmaxf(acc[q], 0.0f);
-        p1[q] = (__bf16)fmaxf(acc[8 + q], 0.0f);
-    }
+    bf16x8 p0 = relu_bf16(acc, 0), p1 = relu_bf16(acc, 8);
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[v] = m->b2[8 * (v >> 2) + 4 * h + (v & 3)];
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(m->A2[0][lane], p0, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(m->A2[1][lane], p1, acc, 0, 0, 0);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        p0[q] = (__bf16)fmaxf(acc[q], 0.0f);
-        p1[q] = (__bf16)fmaxf(acc[8 + q], 0.0f);
-    }
+    p0 = relu_bf16(acc, 0);
+    p1 = relu_bf16(acc, 8);
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(m->A3[0][lane], p0, acc, 0, 0, 0);
@@ -127,20 +131,29 @@ __host__ __device__ inline void mlp_beta(const float* x, float* b)
     b[2] = 13.0f / 12.0f * a2 * a2 + 0.25f * c2 * c2;
 }
 
+// tanh(x) = 1 - 2/(e^{2x} + 1) from the hardware exponential and
+// reciprocal: absolute error of a few 1e-8, which is what matters where the
+// value is an exponent (large |x| gives +-1, NaN stays NaN)
+__device__ inline float mlp_tanh(float x)
+{
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__expf(2.0f * x) + 1.0f);
+}
+
 // omega_k = d_k e^{tanh z_k} / (eps + beta_k)^2, normalised: the network
 // rescales each classical weight of the normalised stencil x by a factor in
-// [1/e, e]; false if a weight is not finite
+// [1/e, e]; false if a weight is not finite.  Exponentials and reciprocals
+// are the hardware ones (float, about an ulp): the weights are float anyway.
 __device__ inline bool mlp_omega(const float* z, const float* x, float* w)
 {
     float b[3];
     mlp_beta(x, b);
-    const float t0 = tanhf(z[0]), t1 = tanhf(z[1]), t2 = tanhf(z[2]);
+    const float t0 = mlp_tanh(z[0]), t1 = mlp_tanh(z[1]), t2 = mlp_tanh(z[2]);
     const float mx = fmaxf(t0, fmaxf(t1, t2));
     const float q0 = MLP_EPS + b[0], q1 = MLP_EPS + b[1], q2 = MLP_EPS + b[2];
-    const float a0 = 0.0625f * expf(t0 - mx) / (q0 * q0);
-    const float a1 = 0.625f * expf(t1 - mx) / (q1 * q1);
-    const float a2 = 0.3125f * expf(t2 - mx) / (q2 * q2);
-    const float is = 1.0f / (a0 + a1 + a2);
+    const float a0 = 0.0625f * __expf(t0 - mx) * __builtin_amdgcn_rcpf(q0 * q0);
+    const float a1 = 0.625f * __expf(t1 - mx) * __builtin_amdgcn_rcpf(q1 * q1);
+    const float a2 = 0.3125f * __expf(t2 - mx) * __builtin_amdgcn_rcpf(q2 * q2);
+    const float is = __builtin_amdgcn_rcpf(a0 + a1 + a2);
     w[0] = a0 * is;
     w[1] = a1 * is;
     w[2] = a2 * is;

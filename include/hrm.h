@@ -59,7 +59,7 @@ extern "C" {
 #define HRM_NO_BLEND 2      /* shock-sensor blending off: pure HCS flux (App. B) */
 #define HRM_FIRST_ORDER 4   /* first-order HLLC fluxes only (Sec. 4.1.1) */
 #define HRM_FUSE_RELAX 8    /* hrm_rk_stage relaxes its output in the same kernel */
-#define HRM_NO_GRAPH 16     /* hrm_step launches its kernels directly instead of replaying a graph */
+#define HRM_NO_GRAPH 16     /* hrm_advance launches its kernels directly instead of replaying a graph */
 /* HRM_FOUR_EQ: solve the four-equation HRM directly instead of the fractional
  * algorithm (the comparison scheme of Sec. 5.4 and App. A).  The fluxes of
  * alpha_k rho_k, rho u and E are those of the first-order HLLC solver of
@@ -68,7 +68,7 @@ extern "C" {
  * ones, always in double precision; the volume fractions are not evolved (their
  * right-hand side is zero) and are the equilibrium values only where the
  * relaxation runs (HRM_FUSE_RELAX or hrm_relax), for output.  The time step of
- * hrm_compute_dt / hrm_step uses the HRM sound speed.  Implies HRM_FIRST_ORDER;
+ * hrm_compute_dt / hrm_advance uses the HRM sound speed.  Implies HRM_FIRST_ORDER;
  * the limiter, blending and weight settings have no effect. */
 #define HRM_FOUR_EQ 32
 
@@ -128,7 +128,7 @@ void hrm_default_params(hrm_params* p);
 
 /* Validate grid and EOS, copy them into the context and allocate the
  * library's scratch on the current device: one M x ncell right-hand-side
- * buffer (dim > 1), two M x ncell stage buffers for hrm_step, wavespeed
+ * buffer (dim > 1), two M x ncell stage buffers for hrm_advance, wavespeed
  * partials and the counters.  `params` NULL means hrm_default_params().
  * On failure *out is NULL and the code says why (no message store exists). */
 int hrm_create(const hrm_grid* grid, const hrm_eos* eos, const hrm_params* params, hrm_ctx** out);
@@ -177,11 +177,11 @@ int hrm_relax(hrm_ctx* ctx, double* d_W, void* stream);
  * (i_a, i_b = 0 where a dimension is not used), W_b[c] is
  * d_state[c * n_a * n_b + i_a + n_a * i_b], c = 0 .. M-1 in the component
  * order of W.  The states also enter the maximum wavespeed of direction
- * `dim` (hrm_max_wavespeed, hrm_step).  d_state is device memory of the
+ * `dim` (hrm_max_wavespeed, hrm_advance).  d_state is device memory of the
  * caller; it is copied into the context on `stream`, so it may be freed or
  * changed once that copy has run, and later steps see the new state.  Every
  * Dirichlet side must be set before the first hrm_rhs / hrm_rk_stage /
- * hrm_step / hrm_max_wavespeed (HRM_EINVAL otherwise).  HRM_EINVAL if the
+ * hrm_advance / hrm_max_wavespeed (HRM_EINVAL otherwise).  HRM_EINVAL if the
  * side is not Dirichlet or d_state is NULL. */
 int hrm_set_boundary_state(hrm_ctx* ctx, int dim, int side, const double* d_state, void* stream);
 
@@ -253,13 +253,27 @@ int hrm_mlp_grad(const float* d_params, const float* d_X, const float* d_T, long
 int hrm_mlp_adam(float* d_params, const float* d_grad, float* d_m, float* d_v, int step, float lr, float beta1,
                  float beta2, float eps, void* stream);
 
-/* One full SSP-RK3 step of the fractional algorithm on d_W in place:
- * wavespeed of W^n, time step into d_slot (see hrm_compute_dt), three stages
- * each followed by the relaxation.  Uses the context's stage buffers.
- * Unless the grid has HRM_NO_GRAPH (or timing is on), the first call captures
- * the step's launches into a hipGraph on a private stream and every call with
- * the same (d_W, d_slot, cfl, dt_fixed, t_end) replays it on `stream`; other
- * arguments re-capture.  The graph holds kernel nodes only. */
+/* `nsteps` full SSP-RK3 steps of the fractional algorithm (Sec. 4: the
+ * stages of Sec. 4.1 each followed by the relaxation of Sec. 4.2) on d_W in
+ * place.  Each step takes its time step from the maximum of |u_d| + c of
+ * W^n (Sec. 4.1.2; into d_slot as hrm_compute_dt writes it, with the device
+ * time slot[4] advanced and clipped to t_end), then runs three stages with
+ * the context's stage buffers, relaxing each stage's output.  The maxima of
+ * the first step are taken by a pass over d_W; those of every later step
+ * by the last sweep of the step before, from the cells it has just written
+ * (the same values, so the result equals nsteps calls of hrm_step to the
+ * bit).  d_W (M x ncell, component-major) and d_slot (>= 5 doubles) are the
+ * caller's device memory; nothing else in d_W may change during the call.
+ * Unless the grid has HRM_NO_GRAPH (or timing is on), the step's launches
+ * are captured once into a hipGraph on a private stream and replayed on
+ * `stream` for every step with the same (d_W, d_slot, cfl, dt_fixed,
+ * t_end); other arguments re-capture.  The graph holds kernel nodes only.
+ * HRM_EINVAL for NULL pointers, nsteps < 0, or neither cfl nor dt_fixed
+ * positive; nsteps == 0 launches nothing. */
+int hrm_advance(hrm_ctx* ctx, double* d_W, int nsteps, double cfl, double dt_fixed, double t_end, double* d_slot,
+                void* stream);
+
+/* hrm_advance with nsteps = 1. */
 int hrm_step(hrm_ctx* ctx, double* d_W, double cfl, double dt_fixed, double t_end, double* d_slot,
              void* stream);
 

@@ -9,9 +9,14 @@
 //                     in LDS, computes one face per thread, writes the face
 //                     pairs back to LDS and forms the flux difference of each
 //                     cell.  The last direction also applies the Shu-Osher
-//                     stage update and, optionally, the relaxation.
+//                     stage update and, optionally, the relaxation; in the
+//                     last stage of a step it also folds the block maxima
+//                     of |u_d| + c of the new state into the partial slots
+//                     of the next step's time step.
 //   k_relax           point-wise relaxation.
-//   k_wavespeed       per-block max of |u_d| + c, then k_reduce_max.
+//   k_wavespeed       per-block max of |u_d| + c (the first step of a run,
+//                     hrm_max_wavespeed), then k_reduce_max / k_reduce_dt
+//                     (which clears the slots the sweep folds into).
 //   k_dt              the time step and lambda_d on the device.
 #include <hip/hip_runtime.h>
 
@@ -37,6 +42,8 @@ struct SweepArgs {
     int bclo, bchi;
     const double* blo;  // Dirichlet ghost states of the low / high face (M x face cells), or null
     const double* bhi;
+    double* wpart;  // mode 2, non-null: maxima of |u_d| + c of the stage output, block b into slot b % nslot
+    unsigned nslot; // a power of two, at most the number of blocks
     int mode;  // 0: rhs = L_d, 1: rhs += L_d, 2: stage update with rhs + L_d
     int relax;
     double a, b;
@@ -46,6 +53,35 @@ struct SweepArgs {
 };
 
 constexpr int MODE_WRITE = 0, MODE_ADD = 1, MODE_FINAL = 2;
+
+// one DPP move of a 64-bit value (both halves with the same control); rows
+// outside ROWS keep their own value
+template <int CTRL, int ROWS>
+__device__ inline unsigned long long dpp_u64(unsigned long long v)
+{
+    const int lo = (int)(unsigned)v, hi = (int)(unsigned)(v >> 32);
+    const int l = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xF, false);
+    const int h = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xF, false);
+    return ((unsigned long long)(unsigned)h << 32) | (unsigned)l;
+}
+
+__device__ inline unsigned long long umax64(unsigned long long a, unsigned long long b) { return a > b ? a : b; }
+
+// maximum of a 64-bit unsigned value over the wave (all 64 lanes active),
+// returned in every lane: within each row of 16 lanes by quad permutes and
+// mirrors, then across rows by the row broadcasts, read back from lane 63
+__device__ inline unsigned long long wave_umax64(unsigned long long v)
+{
+    v = umax64(v, dpp_u64<0xB1, 0xF>(v));   // quad_perm [1,0,3,2]
+    v = umax64(v, dpp_u64<0x4E, 0xF>(v));   // quad_perm [2,3,0,1]
+    v = umax64(v, dpp_u64<0x141, 0xF>(v));  // row_half_mirror
+    v = umax64(v, dpp_u64<0x140, 0xF>(v));  // row_mirror: row maximum in every lane
+    v = umax64(v, dpp_u64<0x142, 0xA>(v));  // row_bcast:15 into rows 1 and 3
+    v = umax64(v, dpp_u64<0x143, 0xC>(v));  // row_bcast:31 into rows 2 and 3
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
+    return ((unsigned long long)hi << 32) | lo;
+}
 
 // Tile: BS face threads along the sweep direction (BS-1 cells), BA threads
 // across it.  DIR == 0: blockDim = (BS, BA), across = y, blockIdx.z = z.
@@ -58,7 +94,10 @@ constexpr int MODE_WRITE = 0, MODE_ADD = 1, MODE_FINAL = 2;
 // 256^3 FP64 +3 %, FP32 +11 %.
 constexpr int SWEEP_WAVES = 3;
 
-template <int N, int D, int DIR, int BS, int BA, typename R, int WT>
+// WS: the launch is a stage update that also folds the wavespeed maxima of
+// its output into A.wpart; a separate instantiation, so that the other
+// launches keep their register allocation
+template <int N, int D, int DIR, int BS, int BA, typename R, int WT, bool WS = false>
 __global__ void __launch_bounds__(BS* BA, SWEEP_WAVES) k_sweep(const SweepArgs A)
 {
     using F = NodeFields<N, D>;
@@ -67,6 +106,7 @@ __global__ void __launch_bounds__(BS* BA, SWEEP_WAVES) k_sweep(const SweepArgs A
     constexpr int LN = BS + 5;
     constexpr int FS = BA * LN;
     constexpr int NS = DIR == 0 ? 1 : BA;
+    static_assert((BS * BA) % 64 == 0, "whole waves");
     __shared__ double lds[F::COUNT * FS];
 
     const int ts = DIR == 0 ? threadIdx.x : threadIdx.y;
@@ -156,6 +196,9 @@ __global__ void __launch_bounds__(BS* BA, SWEEP_WAVES) k_sweep(const SweepArgs A
 
     // flux difference of cell c0+ts: faces ts (i-1/2) and ts+1 (i+1/2)
     const int ci = c0 + ts, ca = abase + ta;
+    double wmax[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) wmax[d] = 0.0;
     if (ts < BS - 1 && ci < nsw && ca < na) {
         const long long cell = ci * st[DIR] + ca * st[adim] + other * st[odim];
         const int bl = base(ta, ts), br = base(ta, ts + 1);
@@ -181,6 +224,43 @@ __global__ void __launch_bounds__(BS* BA, SWEEP_WAVES) k_sweep(const SweepArgs A
             if (A.relax && !relax_cell<N, D>(A.e, w)) cnt[C_RELAX_BAD]++;
 #pragma unroll
             for (int c = 0; c < M; ++c) A.Wout[c * nc + cell] = w[c];
+            if constexpr (WS) {
+                // Sec. 4.1.2: |u_d| + c of the new state, for the next time step
+                St<N, D> s;
+                state_from_W<N, D>(A.e, w, s);
+                double cs = s.c;
+                if (A.P.flags & F_FOUR_EQ) {
+                    double p;
+                    hrm4_pc<N, D>(A.e, s, p, cs);
+                }
+#pragma unroll
+                for (int d = 0; d < D; ++d) wmax[d] = fabs(s.u[d]) + cs;
+            }
+        }
+    }
+    if constexpr (WS) {
+        // block maximum, folded into slot (linear block index) % nslot, which
+        // the time-step reduction has cleared.  The values are +0 or above,
+        // or NaN; their bit patterns order as unsigned integers the same way,
+        // with every NaN above every number, so the maximum is taken on the
+        // bits: without branches, and by the 64-bit unsigned atomic max
+        __shared__ unsigned long long wsh[(BS * BA / 64) * D];
+        unsigned long long wb[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) wb[d] = wave_umax64((unsigned long long)__double_as_longlong(wmax[d]));
+        if ((tid & 63) == 0)
+#pragma unroll
+            for (int d = 0; d < D; ++d) wsh[(tid >> 6) * D + d] = wb[d];
+        __syncthreads();
+        if (tid == 0) {
+#pragma unroll
+            for (int i = 1; i < BS * BA / 64; ++i)
+#pragma unroll
+                for (int d = 0; d < D; ++d) wb[d] = umax64(wb[d], wsh[i * D + d]);
+            const unsigned blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+            unsigned long long* slot = (unsigned long long*)A.wpart + (blk & (A.nslot - 1u)) * D;
+#pragma unroll
+            for (int d = 0; d < D; ++d) atomicMax(slot + d, wb[d]);
         }
     }
     flush_counters(cnt, A.cnt);
@@ -237,17 +317,20 @@ __global__ void __launch_bounds__(256) k_wavespeed(const double* W, long long nc
         for (int d = 0; d < D; ++d) part[blockIdx.x * D + d] = m[d];
 }
 
-// this thread's share of the maximum of nb partials (one block of 256
+// threads of the one-block reductions of the partials
+constexpr int RT = 256;
+
+// this thread's share of the maximum of nb partials (one block of RT
 // threads): eight loads in flight per pass instead of one
 template <int D>
 __device__ inline void partial_max(const double* part, int nb, double* m)
 {
-    for (int i0 = threadIdx.x; i0 < nb; i0 += 256 * 8) {
+    for (int i0 = threadIdx.x; i0 < nb; i0 += RT * 8) {
         double v[8][D];
 #pragma unroll
         for (int u = 0; u < 8; ++u)
 #pragma unroll
-            for (int d = 0; d < D; ++d) v[u][d] = i0 + 256 * u < nb ? part[(i0 + 256 * u) * D + d] : 0.0;
+            for (int d = 0; d < D; ++d) v[u][d] = i0 + RT * u < nb ? part[(i0 + RT * u) * D + d] : 0.0;
 #pragma unroll
         for (int u = 0; u < 8; ++u)
 #pragma unroll
@@ -256,9 +339,9 @@ __device__ inline void partial_max(const double* part, int nb, double* m)
 }
 
 template <int D>
-__global__ void __launch_bounds__(256) k_reduce_max(const double* part, int nb, double* out)
+__global__ void __launch_bounds__(RT) k_reduce_max(const double* part, int nb, double* out)
 {
-    __shared__ double sh[4 * 3];
+    __shared__ double sh[(RT / 64) * 3];
     double m[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) m[d] = 0.0;
@@ -297,15 +380,21 @@ __global__ void k_dt(const double* maxs, DtArgs a, double* slot)
     if (threadIdx.x == 0 && blockIdx.x == 0) dt_from_max(maxs, a, slot);
 }
 
-// grid-wide maximum of the wavespeed partials and the time step, one block
+// grid-wide maximum of the wavespeed partials and the time step, one block;
+// then the first nclear partials (the slots the last sweep of the step folds
+// into) are set to +0, each by the thread that read it
 template <int D>
-__global__ void __launch_bounds__(256) k_reduce_dt(const double* part, int nb, double* maxs, DtArgs a, double* slot)
+__global__ void __launch_bounds__(RT) k_reduce_dt(double* part, int nb, int nclear, double* maxs, DtArgs a,
+                                                   double* slot)
 {
-    __shared__ double sh[4 * 3];
+    __shared__ double sh[(RT / 64) * 3];
     double m[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) m[d] = 0.0;
     partial_max<D>(part, nb, m);
+    for (int i = threadIdx.x; i < nclear; i += RT)
+#pragma unroll
+        for (int d = 0; d < D; ++d) part[i * D + d] = 0.0;
     block_max<D>(m, sh);
     if (threadIdx.x == 0) {
 #pragma unroll
@@ -356,7 +445,8 @@ struct hrm_ctx {
     double* d_W1;
     double* d_W2;
     double* d_part;
-    int npart;
+    int npart;               // wavespeed partial blocks of hrm_max_wavespeed
+    int nslot;               // partial slots the last sweep of a step folds its blocks into
     double* d_maxs;
     unsigned long long* d_cnt;
     double* d_bnd[3][2];     // Dirichlet ghost states per face (M x face cells), null elsewhere
@@ -439,6 +529,29 @@ struct TimerScope {
     }
 };
 
+// tile of the sweep in direction dir: BS face threads along it, BA across
+void sweep_tile(int D, int dir, int& BS, int& BA)
+{
+    if (D == 1) {
+        BS = 256;
+        BA = 1;
+    } else if (dir == 0) {
+        BS = 64;
+        BA = 4;
+    } else {
+        BS = 16;
+        BA = 16;
+    }
+}
+
+dim3 sweep_grid(const hrm_ctx* c, int dir, int BS, int BA)
+{
+    const int cells = BS - 1;
+    if (dir == 0) return dim3((c->n[0] + cells - 1) / cells, (c->n[1] + BA - 1) / BA, c->n[2]);
+    if (dir == 1) return dim3((c->n[0] + BA - 1) / BA, (c->n[1] + cells - 1) / cells, c->n[2]);
+    return dim3((c->n[0] + BA - 1) / BA, c->n[1], (c->n[2] + cells - 1) / cells);
+}
+
 template <int N, int D>
 struct Ops {
     static constexpr int M = 2 * N + D;
@@ -447,33 +560,39 @@ struct Ops {
     static void launch_dir(hrm_ctx* c, hrm::SweepArgs& A, hipStream_t s)
     {
         dim3 blk = DIR == 0 ? dim3(BS, BA) : dim3(BA, BS);
-        const int cells = BS - 1;
-        dim3 grd;
-        if (DIR == 0)
-            grd = dim3((c->n[0] + cells - 1) / cells, (c->n[1] + BA - 1) / BA, c->n[2]);
-        else if (DIR == 1)
-            grd = dim3((c->n[0] + BA - 1) / BA, (c->n[1] + cells - 1) / cells, c->n[2]);
-        else
-            grd = dim3((c->n[0] + BA - 1) / BA, c->n[1], (c->n[2] + cells - 1) / cells);
+        const dim3 grd = sweep_grid(c, DIR, BS, BA);
         A.bclo = c->bclo[DIR];
         A.bchi = c->bchi[DIR];
         A.blo = c->d_bnd[DIR][0];
         A.bhi = c->d_bnd[DIR][1];
         A.idx = 1.0 / c->dx[DIR];
         TimerScope t(c, HRM_T_SWEEP_X + DIR, s);
+        if constexpr (DIR == D - 1) {
+            if (A.wpart) {
+                launch_kernel<DIR, BS, BA, true>(c, A, grd, blk, s);
+                return;
+            }
+        }
+        launch_kernel<DIR, BS, BA, false>(c, A, grd, blk, s);
+    }
+
+    template <int DIR, int BS, int BA, bool WS>
+    static void launch_kernel(hrm_ctx* c, const hrm::SweepArgs& A, dim3 grd, dim3 blk, hipStream_t s)
+    {
         if constexpr (D <= 2) {
             // learned weights: FP64 face arithmetic, one and two dimensions
             if (c->weights == HRM_WEIGHTS_MLP) {
-                hipLaunchKernelGGL((hrm::k_sweep<N, D, DIR, BS, BA, double, 1>), grd, blk, 0, s, A);
+                hipLaunchKernelGGL((hrm::k_sweep<N, D, DIR, BS, BA, double, 1, WS>), grd, blk, 0, s, A);
                 return;
             }
         }
         if (c->precision == HRM_FP32)
-            hipLaunchKernelGGL((hrm::k_sweep<N, D, DIR, BS, BA, float, 0>), grd, blk, 0, s, A);
+            hipLaunchKernelGGL((hrm::k_sweep<N, D, DIR, BS, BA, float, 0, WS>), grd, blk, 0, s, A);
         else
-            hipLaunchKernelGGL((hrm::k_sweep<N, D, DIR, BS, BA, double, 0>), grd, blk, 0, s, A);
+            hipLaunchKernelGGL((hrm::k_sweep<N, D, DIR, BS, BA, double, 0, WS>), grd, blk, 0, s, A);
     }
 
+    // tiles as sweep_tile gives them
     static void sweep(hrm_ctx* c, int dir, hrm::SweepArgs& A, hipStream_t s)
     {
         if constexpr (D == 1) {
@@ -493,14 +612,14 @@ struct Ops {
         hipLaunchKernelGGL((hrm::k_relax<N, D>), dim3((unsigned)nb), dim3(256), 0, s, W, c->ncell, c->eos, c->d_cnt);
     }
 
-    // per-block maxima of the cells, then of the Dirichlet ghost states;
-    // returns the number of partial blocks
-    static int wavespeed_parts(hrm_ctx* c, const double* W, hipStream_t s)
+    // per-block maxima of the cells (ncb blocks), then of the Dirichlet ghost
+    // states; returns the number of partial blocks
+    static int wavespeed_parts(hrm_ctx* c, const double* W, int ncb, hipStream_t s)
     {
         const int four = (c->flags & HRM_FOUR_EQ) ? 1 : 0;
-        hipLaunchKernelGGL((hrm::k_wavespeed<N, D>), dim3(c->npart), dim3(256), 0, s, W, c->ncell, c->eos, four, -1,
+        hipLaunchKernelGGL((hrm::k_wavespeed<N, D>), dim3(ncb), dim3(256), 0, s, W, c->ncell, c->eos, four, -1,
                            c->d_part);
-        int nb = c->npart;
+        int nb = ncb;
         for (int d = 0; d < D; ++d)
             for (int side = 0; side < 2; ++side)
                 if (c->d_bnd[d][side]) {
@@ -511,18 +630,31 @@ struct Ops {
         return nb;
     }
 
-    static void wavespeed_dt(hrm_ctx* c, const double* W, const hrm::DtArgs& a, double* slot, hipStream_t s)
+    // the partials of W in the layout of the final sweep's: nslot slots,
+    // then the Dirichlet ghost states
+    static void seed_parts(hrm_ctx* c, const double* W, hipStream_t s)
     {
         TimerScope t(c, HRM_T_WAVESPEED, s);
-        const int nb = wavespeed_parts(c, W, s);
-        hipLaunchKernelGGL((hrm::k_reduce_dt<D>), dim3(1), dim3(256), 0, s, c->d_part, nb, c->d_maxs, a, slot);
+        (void)wavespeed_parts(c, W, c->nslot, s);
+    }
+
+    // the time step from the partials of seed_parts or of the last final sweep
+    static void reduce_dt(hrm_ctx* c, const hrm::DtArgs& a, double* slot, hipStream_t s)
+    {
+        TimerScope t(c, HRM_T_WAVESPEED, s);
+        int nb = c->nslot;
+        for (int d = 0; d < D; ++d)
+            for (int side = 0; side < 2; ++side)
+                if (c->d_bnd[d][side]) nb += c->nbpart[d];
+        hipLaunchKernelGGL((hrm::k_reduce_dt<D>), dim3(1), dim3(hrm::RT), 0, s, c->d_part, nb, c->nslot, c->d_maxs, a,
+                           slot);
     }
 
     static void wavespeed(hrm_ctx* c, const double* W, double* out, hipStream_t s)
     {
         TimerScope t(c, HRM_T_WAVESPEED, s);
-        const int nb = wavespeed_parts(c, W, s);
-        hipLaunchKernelGGL((hrm::k_reduce_max<D>), dim3(1), dim3(256), 0, s, c->d_part, nb, out);
+        const int nb = wavespeed_parts(c, W, c->npart, s);
+        hipLaunchKernelGGL((hrm::k_reduce_max<D>), dim3(1), dim3(hrm::RT), 0, s, c->d_part, nb, out);
     }
 };
 
@@ -554,9 +686,10 @@ hrm::SweepArgs base_args(hrm_ctx* c)
 
 int check_boundary(hrm_ctx* c);
 
-// all directions of L(W_s); the last one runs in `final_mode`
+// all directions of L(W_s); with `stage` the last one applies the stage
+// update (and writes the wavespeed partials of its output into wpart)
 int run_operator(hrm_ctx* c, const double* Ws, const double* Wn, double* Wout, double* rhs, const double* slot,
-                 bool stage, double a, double b, int relax, hipStream_t s)
+                 bool stage, double a, double b, int relax, hipStream_t s, double* wpart = nullptr)
 {
     if (c->weights == HRM_WEIGHTS_MLP && !c->mlp_ready)
         return fail(c, HRM_EINVAL, "learned weights selected but hrm_set_mlp not called%s");
@@ -570,6 +703,8 @@ int run_operator(hrm_ctx* c, const double* Ws, const double* Wn, double* Wout, d
     A.a = a;
     A.b = b;
     A.relax = relax;
+    A.wpart = stage ? wpart : nullptr;
+    A.nslot = (unsigned)c->nslot;
     int rc = HRM_OK;
     for (int d = 0; d < c->D; ++d) {
         const bool last = d == c->D - 1;
@@ -605,18 +740,31 @@ hrm::DtArgs dt_args(hrm_ctx* c, double cfl, double dt_fixed, double t_end)
     return a;
 }
 
-// the launches of one RK3 step on stream s
+// the wavespeed partials of W^n for the first step of a run (the later
+// steps find them written by the final sweep of the step before)
+int seed_enqueue(hrm_ctx* c, const double* d_W, hipStream_t s)
+{
+    int rc = check_boundary(c);
+    if (rc == HRM_OK) rc = dispatch(c, [&](auto ops) { decltype(ops)::seed_parts(c, d_W, s); });
+    if (rc == HRM_OK) rc = check_launch(c, "hrm_advance wavespeed");
+    return rc;
+}
+
+// the launches of one RK3 step on stream s: time step from the partials,
+// three stages with the relaxation, the last one leaving the partials of
+// W^{n+1}
 int step_enqueue(hrm_ctx* c, double* d_W, double cfl, double dt_fixed, double t_end, double* d_slot, hipStream_t s)
 {
     static const double RK_A[3] = {0.0, 3.0 / 4.0, 1.0 / 3.0};
     static const double RK_B[3] = {1.0, 1.0 / 4.0, 2.0 / 3.0};
     const hrm::DtArgs a = dt_args(c, cfl, dt_fixed, t_end);
     int rc = check_boundary(c);
-    if (rc == HRM_OK) rc = dispatch(c, [&](auto ops) { decltype(ops)::wavespeed_dt(c, d_W, a, d_slot, s); });
-    if (rc == HRM_OK) rc = check_launch(c, "hrm_step wavespeed");
+    if (rc == HRM_OK) rc = dispatch(c, [&](auto ops) { decltype(ops)::reduce_dt(c, a, d_slot, s); });
+    if (rc == HRM_OK) rc = check_launch(c, "hrm_advance time step");
     if (rc == HRM_OK) rc = run_operator(c, d_W, d_W, c->d_W1, c->d_rhs, d_slot, true, RK_A[0], RK_B[0], 1, s);
     if (rc == HRM_OK) rc = run_operator(c, c->d_W1, d_W, c->d_W2, c->d_rhs, d_slot, true, RK_A[1], RK_B[1], 1, s);
-    if (rc == HRM_OK) rc = run_operator(c, c->d_W2, d_W, d_W, c->d_rhs, d_slot, true, RK_A[2], RK_B[2], 1, s);
+    if (rc == HRM_OK)
+        rc = run_operator(c, c->d_W2, d_W, d_W, c->d_rhs, d_slot, true, RK_A[2], RK_B[2], 1, s, c->d_part);
     return rc;
 }
 
@@ -738,7 +886,17 @@ int hrm_create(const hrm_grid* g, const hrm_eos* e, const hrm_params* prm, hrm_c
 
     const size_t bytes = sizeof(double) * (size_t)c->M * (size_t)c->ncell;
     c->npart = (int)std::min<long long>((c->ncell + 255) / 256, 2048);
-    int nparts = c->npart;
+    {
+        int BS, BA;
+        sweep_tile(c->D, c->D - 1, BS, BA);
+        const dim3 g = sweep_grid(c, c->D - 1, BS, BA);
+        // the largest power of two up to the block count and 2048, so that
+        // every slot receives at least one block
+        const long long nblk = (long long)g.x * g.y * g.z;
+        c->nslot = 1;
+        while (c->nslot < 2048 && 2ll * c->nslot <= nblk) c->nslot *= 2;
+    }
+    int nparts = std::max(c->npart, c->nslot);
     for (int d = 0; d < 3; ++d) {
         c->nface[d] = c->ncell / c->n[d];
         c->nbpart[d] = (int)std::min<long long>((c->nface[d] + 255) / 256, 256);
@@ -900,32 +1058,42 @@ int hrm_mlp_infer(hrm_ctx* c, const double* d_U5, long long n, double* d_val, fl
     return check_launch(c, "hrm_mlp_infer");
 }
 
-int hrm_step(hrm_ctx* c, double* d_W, double cfl, double dt_fixed, double t_end, double* d_slot, void* stream)
+int hrm_advance(hrm_ctx* c, double* d_W, int nsteps, double cfl, double dt_fixed, double t_end, double* d_slot,
+                void* stream)
 {
     if (!c) return HRM_EINVAL;
-    if (!valid_ptr(d_W) || !valid_ptr(d_slot)) return fail(c, HRM_EINVAL, "hrm_step: NULL pointer%s");
-    if (!(dt_fixed > 0.0) && !(cfl > 0.0)) return fail(c, HRM_EINVAL, "hrm_step: need cfl > 0 or dt_fixed > 0%s");
+    if (!valid_ptr(d_W) || !valid_ptr(d_slot)) return fail(c, HRM_EINVAL, "hrm_advance: NULL pointer%s");
+    if (nsteps < 0) return fail(c, HRM_EINVAL, "hrm_advance: nsteps = %s%lld < 0", "", nsteps);
+    if (!(dt_fixed > 0.0) && !(cfl > 0.0)) return fail(c, HRM_EINVAL, "hrm_advance: need cfl > 0 or dt_fixed > 0%s");
+    if (c->weights == HRM_WEIGHTS_MLP && !c->mlp_ready)
+        return fail(c, HRM_EINVAL, "learned weights selected but hrm_set_mlp not called%s");
+    if (nsteps == 0) return HRM_OK;
     hipStream_t s = (hipStream_t)stream;
     c->last_stream = s;
-    if ((c->flags & HRM_NO_GRAPH) || c->timing_mask) return step_enqueue(c, d_W, cfl, dt_fixed, t_end, d_slot, s);
+    int rc = seed_enqueue(c, d_W, s);
+    if (rc != HRM_OK) return rc;
+    if ((c->flags & HRM_NO_GRAPH) || c->timing_mask) {
+        for (int k = 0; k < nsteps && rc == HRM_OK; ++k) rc = step_enqueue(c, d_W, cfl, dt_fixed, t_end, d_slot, s);
+        return rc;
+    }
     const bool same = c->gexec && c->g_W == d_W && c->g_slot == d_slot && c->g_cfl == cfl &&
                       c->g_dt_fixed == dt_fixed && c->g_t_end == t_end;
     if (!same) {
         drop_graph(c);
         if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess)
-            return fail(c, HRM_EDEVICE, "hrm_step: stream capture failed%s");
-        const int rc = step_enqueue(c, d_W, cfl, dt_fixed, t_end, d_slot, c->cap_stream);
+            return fail(c, HRM_EDEVICE, "hrm_advance: stream capture failed%s");
+        rc = step_enqueue(c, d_W, cfl, dt_fixed, t_end, d_slot, c->cap_stream);
         hipGraph_t g = nullptr;
         const hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
         if (rc != HRM_OK || ec != hipSuccess || !g) {
             if (g) (void)hipGraphDestroy(g);
-            return rc != HRM_OK ? rc : fail(c, HRM_EDEVICE, "hrm_step: end capture: %s", hipGetErrorString(ec));
+            return rc != HRM_OK ? rc : fail(c, HRM_EDEVICE, "hrm_advance: end capture: %s", hipGetErrorString(ec));
         }
         const hipError_t ei = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (ei != hipSuccess) {
             c->gexec = nullptr;
-            return fail(c, HRM_EDEVICE, "hrm_step: graph instantiate: %s", hipGetErrorString(ei));
+            return fail(c, HRM_EDEVICE, "hrm_advance: graph instantiate: %s", hipGetErrorString(ei));
         }
         c->g_W = d_W;
         c->g_slot = d_slot;
@@ -933,9 +1101,15 @@ int hrm_step(hrm_ctx* c, double* d_W, double cfl, double dt_fixed, double t_end,
         c->g_dt_fixed = dt_fixed;
         c->g_t_end = t_end;
     }
-    if (hipGraphLaunch(c->gexec, s) != hipSuccess)
-        return fail(c, HRM_EDEVICE, "hrm_step: graph launch: %s", hipGetErrorString(hipGetLastError()));
+    for (int k = 0; k < nsteps; ++k)
+        if (hipGraphLaunch(c->gexec, s) != hipSuccess)
+            return fail(c, HRM_EDEVICE, "hrm_advance: graph launch: %s", hipGetErrorString(hipGetLastError()));
     return HRM_OK;
+}
+
+int hrm_step(hrm_ctx* c, double* d_W, double cfl, double dt_fixed, double t_end, double* d_slot, void* stream)
+{
+    return hrm_advance(c, d_W, 1, cfl, dt_fixed, t_end, d_slot, stream);
 }
 
 int hrm_get_diagnostics(hrm_ctx* c, hrm_diag* out)

@@ -95,9 +95,10 @@ __device__ inline R sensor_ratio_t(R v0, R v1, R v2, R v3, R v4)
 // Output: G = G^{**,-}_{i+1/2} (M slots) and Gp = alpha slots of G^{**,+}.
 // R is the face arithmetic type; node data, the flux limiter and the outputs
 // are double.  LOW = false leaves out the first-order and direct-HRM branches
-// (selected by flags) for callers that never take them.
+// (selected by flags) for callers that never take them.  Always inlined:
+// a call would spill the whole face state around it.
 template <int N, int D, int DIR, int NS, int FS, typename R, int WT = 0, bool LOW = true>
-__device__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, double lam, double* G, double* Gp,
+__device__ __forceinline__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, double lam, double* G, double* Gp,
                           unsigned* cnt)
 {
     using F = NodeFields<N, D>;

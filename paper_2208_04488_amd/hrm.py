@@ -80,6 +80,7 @@ def _load():
     L.hrm_relax.argtypes = [vp, vp, vp]
     L.hrm_set_boundary_state.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp]
     L.hrm_step.argtypes = [vp, vp, dp, dp, dp, vp, vp]
+    L.hrm_advance.argtypes = [vp, vp, ctypes.c_int, dp, dp, dp, vp, vp]
     L.hrm_get_diagnostics.argtypes = [vp, ctypes.POINTER(hrm_diag)]
     L.hrm_reset_diagnostics.argtypes = [vp, vp]
     L.hrm_set_timing.argtypes = [vp, ctypes.c_int]
@@ -202,6 +203,11 @@ def hrm_set_boundary_state(ctx, dim, side, state, stream=None):
 def hrm_step(ctx, W, cfl, dt_fixed, t_end, slot, stream=None):
     return _check(ctx, lib.hrm_step(ctx, _ptr(W), float(cfl), float(dt_fixed), float(t_end), _ptr(slot),
                                     _stream(stream)))
+
+
+def hrm_advance(ctx, W, nsteps, cfl, dt_fixed, t_end, slot, stream=None):
+    return _check(ctx, lib.hrm_advance(ctx, _ptr(W), int(nsteps), float(cfl), float(dt_fixed), float(t_end),
+                                       _ptr(slot), _stream(stream)))
 
 
 def hrm_get_diagnostics(ctx) -> dict:
@@ -428,6 +434,9 @@ class Solver:
 
     def step(self, cfl=0.4, dt_fixed=0.0, t_end=0.0):
         hrm_step(self.ctx, self.W, cfl, dt_fixed, t_end, self.slot)
+
+    def advance(self, nsteps, cfl=0.4, dt_fixed=0.0, t_end=0.0):
+        hrm_advance(self.ctx, self.W, nsteps, cfl, dt_fixed, t_end, self.slot)
 
     def diagnostics(self):
         return hrm_get_diagnostics(self.ctx)

@@ -68,6 +68,8 @@ def test_null_context_is_rejected(H):
     assert H.lib.hrm_relax(None, None, None) == H.HRM_EINVAL
     assert H.lib.hrm_rk_stage(None, 0, None, None, None, None, None) == H.HRM_EINVAL
     assert H.lib.hrm_destroy(None) == H.HRM_EINVAL
+    assert H.lib.hrm_advance(None, None, 3, 0.4, 0.0, 0.0, None, None) == H.HRM_EINVAL
+    assert H.lib.hrm_step(None, None, 0.4, 0.0, 0.0, None, None) == H.HRM_EINVAL
 
 
 @pytest.mark.parametrize("case", ["nprob0", "first_offset", "empty_problem", "decreasing", "dx0", "dx_nan",

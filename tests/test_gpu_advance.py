@@ -1,0 +1,152 @@
+"""hrm_advance: K SSP-RK3 steps in one call, the maximum wavespeed of every
+step after the first taken by the last sweep of the step before (Sec. 4.1.2
+time step).  The maximum is exact in any order, so the result must equal K
+calls of hrm_step bit for bit (graph replay and direct launches alike), and
+track the oracle's K steps.
+"""
+import numpy as np
+import pytest
+
+from paper_2208_04488_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2208_04488_amd import hrm
+    return hrm
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+def _mlp():
+    from paper_2208_04488_amd import learned
+    return learned.init_params(5, last_scale=0.3)
+
+
+# (problem, flags, precision, learned, steps): ragged tiles in every dimension,
+# Dirichlet sides, the four-equation solver, FP32 faces and learned weights
+CASES = {
+    "config1_364": lambda H: (I.config1(364), 0, H.FP64, False, 6),
+    "config2_130x70": lambda H: (I.config2(130, 70), 0, H.FP64, False, 5),
+    "config3_20": lambda H: (I.config3(20), 0, H.FP64, False, 3),
+    "water_jet_128x64": lambda H: (I.water_jet(128, 64), 0, H.FP64, False, 5),
+    "four_eq_shock_tube": lambda H: (I.shock_tube(400), H.FOUR_EQ, H.FP64, False, 8),
+    "fp32_config2_96x48": lambda H: (I.config2(96, 48), 0, H.FP32, False, 4),
+    "learned_config5_96x48": lambda H: (I.config5(96, 48), 0, H.FP64, True, 4),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_advance_equals_repeated_steps(H, name):
+    import torch
+    prob, flags, prec, mlp, K = CASES[name](H)
+    p = _mlp() if mlp else None
+    runs = {}
+    for kind, fl in (("advance", 0), ("advance_direct", H.NO_GRAPH), ("steps", 0)):
+        s = H.Solver(prob, flags=H.FUSE_RELAX | flags | fl, precision=prec, mlp=p)
+        if kind == "steps":
+            for _ in range(K):
+                s.step(cfl=prob.cfl)
+        else:
+            s.advance(K, cfl=prob.cfl)
+        torch.cuda.synchronize()
+        runs[kind] = (s.W.clone(), s.slot.clone(), s.diagnostics())
+        s.close()
+    Wa, sa, da = runs["advance"]
+    for kind in ("advance_direct", "steps"):
+        W, sl, d = runs[kind]
+        assert torch.equal(Wa, W), (name, kind)
+        assert torch.equal(sa, sl), (name, kind)
+        assert da == d, (name, kind)
+    assert torch.isfinite(Wa).all()
+
+
+@pytest.mark.parametrize("size", ["130x70", "1024x512"])
+def test_advance_tracks_the_oracle(H, orc, size):
+    """K steps of hrm_advance against K oracle steps: the time step of every
+    step (the last one in slot[0], their sum in slot[4]) and the state, at
+    1e-11 relative per step.  1024 x 512 is the benchmark's workload in its
+    launch configuration."""
+    import torch
+    nx, ny = map(int, size.split("x"))
+    prob = I.config2(nx, ny)
+    K = 3
+    o = orc.from_problem(prob)
+    W = prob.W
+    t = 0.0
+    for _ in range(K):
+        W, dt = o.step(W, cfl=prob.cfl)
+        t += dt
+    cmax = o.max_wavespeed(W).max()
+    s = H.Solver(prob, flags=H.FUSE_RELAX)
+    s.set_slot(0.0, [0.0, 0.0], t=0.0)
+    s.advance(K, cfl=prob.cfl)
+    torch.cuda.synchronize()
+    assert s.slot[0].item() == pytest.approx(dt, rel=1e-13)
+    assert s.slot[4].item() == pytest.approx(t, rel=1e-13)
+    got = s.state()
+    N, D, M = prob.N, prob.D, prob.M
+    sc = np.abs(W.reshape(M, -1)).max(axis=1)
+    sc[N:N + D] = max(sc[N:N + D].max(), W[:N].sum(axis=0).max() * cmax)
+    sc[N + D + 1:] = 1.0
+    err = (np.abs(got - W).reshape(M, -1).max(axis=1) / sc).max()
+    print(f"config2 {size}: {K} steps, max rel {err:.2e}")
+    assert err <= K * 1e-11
+    assert s.diagnostics()["relax_bad"] == 0
+    s.close()
+
+
+def test_advance_boundary_state_change_between_calls(H):
+    """A Dirichlet state set between two calls enters the first time step of
+    the second call (its partial maxima are taken again at the start)."""
+    import torch
+    prob = I.water_jet(128, 64)
+    Wb = prob.boundary[(0, 0)].copy()
+    Wb2 = Wb.copy()
+    N = prob.N
+    rho = Wb2[:N].sum(0)
+    u = Wb2[N] / rho
+    Wb2[N] = rho * 2.0 * u
+    Wb2[N + prob.D] += 0.5 * rho * (4.0 - 1.0) * u ** 2
+    outs = []
+    for kind in ("advance", "steps"):
+        s = H.Solver(prob, flags=H.FUSE_RELAX)
+        if kind == "advance":
+            s.advance(3, cfl=prob.cfl)
+            s.set_boundary(0, 0, Wb2)
+            s.advance(3, cfl=prob.cfl)
+        else:
+            for _ in range(3):
+                s.step(cfl=prob.cfl)
+            s.set_boundary(0, 0, Wb2)
+            for _ in range(3):
+                s.step(cfl=prob.cfl)
+        torch.cuda.synchronize()
+        outs.append((s.W.clone(), s.slot.clone()))
+        s.close()
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert torch.equal(outs[0][1], outs[1][1])
+
+
+def test_advance_zero_steps_and_errors(H):
+    import torch
+    prob = I.config2(64, 32)
+    s = H.Solver(prob, flags=H.FUSE_RELAX)
+    W0 = s.W.clone()
+    s.advance(0, cfl=0.4)
+    torch.cuda.synchronize()
+    assert torch.equal(s.W, W0)
+    with pytest.raises(H.HrmError, match="nsteps"):
+        s.advance(-1, cfl=0.4)
+    with pytest.raises(H.HrmError, match="cfl"):
+        s.advance(2, cfl=0.0)
+    s.close()

@@ -32,18 +32,31 @@
 namespace hrm {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// ReLU of 8 accumulator entries, rounded to bfloat16.  The max with 0 is
-// taken on the float bit patterns as 32-bit integers (a float with the sign
-// bit set is a negative integer, -0 included): one integer max per entry,
-// where a float max would first canonicalise its matrix-core operand.
+// ReLU of two floats, rounded to bfloat16 and packed.  Rounding to nearest
+// keeps the sign, so the max with 0 can follow it, taken on the bfloat16
+// bit patterns as 16-bit integers (the sign bit set means a negative
+// integer, -0 and negative NaN included): one packed conversion and one
+// packed integer max per pair, the same bits as the max before the rounding.
+__device__ inline unsigned relu_bf16x2(float a, float b)
+{
+    const bf16x2 c = __builtin_convertvector((f32x2){a, b}, bf16x2);
+    const i16x2 m = __builtin_elementwise_max(__builtin_bit_cast(i16x2, c), (i16x2)0);
+    return __builtin_bit_cast(unsigned, m);
+}
+
+// ReLU of 8 accumulator entries, rounded to bfloat16
 __device__ inline bf16x8 relu_bf16(const f32x16& acc, int base)
 {
-    bf16x8 b;
+    u32x4 r;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) b[q] = (__bf16)__int_as_float(max(__float_as_int(acc[base + q]), 0));
-    return b;
+    for (int q = 0; q < 4; ++q) r[q] = relu_bf16x2(acc[base + 2 * q], acc[base + 2 * q + 1]);
+    return __builtin_bit_cast(bf16x8, r);
 }
 
 constexpr int MLP_NPARAM = 1347;
@@ -53,9 +66,9 @@ constexpr int MLP_OFF_W1 = 0, MLP_OFF_B1 = 160, MLP_OFF_W2 = 192, MLP_OFF_B2 = 1
 // per-lane A-operand fragments (lane l holds row l % 32, K entries
 // 8 (l / 32) .. 8 (l / 32) + 7 of each 16-deep K block)
 struct MlpPacked {
-    bf16x8 A1[64];     // layer 1: K = (x_0..x_4, 1, 0 ... 0)
+    bf16x8 A1[64];     // layer 1: K = (x_0..x_4, 1, 0, 0) twice (K 0..7 and 8..15)
     bf16x8 A2[2][64];  // layer 2: two K blocks over the 32 hidden units
-    bf16x8 A3[2][64];  // layer 3: rows 0..2 are the logits, rows 3..31 zero
+    bf16x8 A3[2][64];  // layer 3: rows 0..2 and again 4..6 are the logits, the rest zero
     float b2[32];
     float b3[4];
 };
@@ -70,7 +83,7 @@ __host__ __device__ inline int mlp_perm(int k)
 }
 
 // one 32-sample column block: xin = this lane's B entries of layer 1; the
-// logits of sample l are returned in lanes l < 32
+// logits of column c are returned in lanes c and 32 + c (rows 0..2 and 4..6)
 __device__ inline void mlp_block(const MlpPacked* __restrict__ m, const bf16x8 xin, float* z)
 {
     const int lane = __lane_id();
@@ -94,28 +107,26 @@ __device__ inline void mlp_block(const MlpPacked* __restrict__ m, const bf16x8 x
     for (int k = 0; k < 3; ++k) z[k] = acc[k] + m->b3[k];
 }
 
-// logits of this lane's sample x[5] (every lane of the wave takes part)
+// logits of this lane's sample x[5] (every lane of the wave takes part).
+// Layer 1's weights fill both halves of K, so each lane feeds its own
+// sample: lanes 0..31 as K 0..7 of the first block (lanes 32..63 zero),
+// lanes 32..63 as K 8..15 of the second (lanes 0..31 zero).
 __device__ inline void mlp_logits(const MlpPacked* __restrict__ m, const float* x, float* z)
 {
     const bool lo = __lane_id() < 32;
-    float xs[5];
-#pragma unroll
-    for (int j = 0; j < 5; ++j) xs[j] = __shfl_xor(x[j], 32, 64);
-    bf16x8 in0, in1;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const float c = q == 5 ? 1.0f : 0.0f;
-        in0[q] = (__bf16)(lo ? (q < 5 ? x[q] : c) : 0.0f);
-        in1[q] = (__bf16)(lo ? (q < 5 ? xs[q] : c) : 0.0f);
-    }
+    u32x4 xv;  // (x_0..x_4, 1, 0, 0) in bfloat16
+    xv[0] = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){x[0], x[1]}, bf16x2));
+    xv[1] = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){x[2], x[3]}, bf16x2));
+    xv[2] = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){x[4], 1.0f}, bf16x2));
+    xv[3] = 0u;
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+    const bf16x8 in0 = __builtin_bit_cast(bf16x8, lo ? xv : zero);
+    const bf16x8 in1 = __builtin_bit_cast(bf16x8, lo ? zero : xv);
     float z0[3], z1[3];
     mlp_block(m, in0, z0);  // samples of lanes 0..31
-    mlp_block(m, in1, z1);  // samples of lanes 32..63, returned in lanes 0..31
+    mlp_block(m, in1, z1);  // samples of lanes 32..63, in their own lanes
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const float s = __shfl_xor(z1[k], 32, 64);
-        z[k] = lo ? z0[k] : s;
-    }
+    for (int k = 0; k < 3; ++k) z[k] = lo ? z0[k] : z1[k];
 }
 
 constexpr float MLP_EPS = 1e-6f;  // of the classical weights, in normalised units
@@ -206,13 +217,14 @@ inline void mlp_pack_host(const float* P, MlpPacked* out)
     for (int lane = 0; lane < 64; ++lane) {
         const int i = lane & 31, h = lane >> 5;
         for (int q = 0; q < 8; ++q) {
-            const int k = 8 * h + q;  // layer 1: inputs, then the constant input of b1
-            const float a1 = k < 5 ? P[MLP_OFF_W1 + k * 32 + i] : (k == 5 ? P[MLP_OFF_B1 + i] : 0.0f);
+            // layer 1, both halves of K: inputs, then the constant input of b1
+            const float a1 = q < 5 ? P[MLP_OFF_W1 + q * 32 + i] : (q == 5 ? P[MLP_OFF_B1 + i] : 0.0f);
             put(out->A1[lane], q, a1);
             for (int kb = 0; kb < 2; ++kb) {
                 const int g = mlp_perm(16 * kb + 8 * h + q);
                 put(out->A2[kb][lane], q, P[MLP_OFF_W2 + g * 32 + i]);
-                put(out->A3[kb][lane], q, i < 3 ? P[MLP_OFF_W3 + g * 3 + i] : 0.0f);
+                const int o = i < 3 ? i : (i >= 4 && i < 7 ? i - 4 : -1);  // logit row
+                put(out->A3[kb][lane], q, o >= 0 ? P[MLP_OFF_W3 + g * 3 + o] : 0.0f);
             }
         }
     }

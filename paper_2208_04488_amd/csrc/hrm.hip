@@ -91,7 +91,8 @@ __device__ inline unsigned long long wave_umax64(unsigned long long v)
 // VGPRs).  For three species that spills ~200 bytes per lane, mostly around
 // the characteristic back-projection, but the third wave hides more LDS and
 // memory latency than the spills cost: 1024 x 512 step 0.441 -> 0.400 ms,
-// 256^3 FP64 +3 %, FP32 +11 %.
+// 256^3 FP64 +3 %, FP32 +11 %.  A fourth wave (128 VGPRs) spills more than
+// it hides: 1024 x 512 step 0.336 -> 0.347 ms, 256^3 FP64 -13 %.
 constexpr int SWEEP_WAVES = 3;
 
 // WS: the launch is a stage update that also folds the wavespeed maxima of

@@ -18,6 +18,9 @@
  *  - Calls return an int status: HRM_OK, or an error code with a message
  *    readable through hrm_last_error().  No exception crosses the ABI.
  *  - Calls on one context are not thread-safe; use one context per thread.
+ *    Work enqueued on one context shares its scratch (stage buffers,
+ *    wavespeed partials, counters): calls on one context that run at the
+ *    same time on different streams race.
  */
 #ifndef HRM_H
 #define HRM_H

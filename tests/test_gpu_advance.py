@@ -105,6 +105,31 @@ def test_advance_tracks_the_oracle(H, orc, size):
     s.close()
 
 
+def test_advance_past_t_end(H, orc):
+    """Steps past t_end: the device time stops at t_end, the later steps
+    take dt = 0, and K steps in one call equal K single steps."""
+    import torch
+    prob = I.config1(200)
+    t_end = 2e-5
+    _, _, k = orc.from_problem(prob).run(prob.W, cfl=0.4, t_end=t_end)
+    K = k + 3
+    outs = []
+    for kind in ("advance", "steps"):
+        s = H.Solver(prob, flags=H.FUSE_RELAX)
+        s.set_slot(0.0, [0.0], t=0.0)
+        if kind == "advance":
+            s.advance(K, cfl=0.4, t_end=t_end)
+        else:
+            for _ in range(K):
+                s.step(cfl=0.4, t_end=t_end)
+        torch.cuda.synchronize()
+        outs.append((s.W.clone(), s.slot.clone()))
+        s.close()
+    assert outs[0][1][4].item() == t_end and outs[0][1][0].item() == 0.0
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert torch.equal(outs[0][1], outs[1][1])
+
+
 def test_advance_boundary_state_change_between_calls(H):
     """A Dirichlet state set between two calls enters the first time step of
     the second call (its partial maxima are taken again at the start)."""

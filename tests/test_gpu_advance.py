@@ -105,6 +105,37 @@ def test_advance_tracks_the_oracle(H, orc, size):
     s.close()
 
 
+def test_advance_full_size_3d(H, orc):
+    """Two steps of the 256^3 three-species workload through hrm_advance:
+    the second step's time step comes from 73 728 z-sweep blocks folded into
+    2048 slots; time steps to 1e-13, every cell to 1e-11 per step."""
+    import torch
+    prob = I.config3(256)
+    K = 2
+    o = orc.from_problem(prob)
+    W = prob.W
+    dts = []
+    for _ in range(K):
+        W, dt = o.step(W, cfl=prob.cfl)
+        dts.append(dt)
+    cmax = o.max_wavespeed(W).max()
+    s = H.Solver(prob, flags=H.FUSE_RELAX)
+    s.set_slot(0.0, [0.0, 0.0, 0.0], t=0.0)
+    s.advance(K, cfl=prob.cfl)
+    torch.cuda.synchronize()
+    assert s.slot[0].item() == pytest.approx(dts[-1], rel=1e-13)
+    assert s.slot[4].item() == pytest.approx(sum(dts), rel=1e-13)
+    got = s.state()
+    s.close()
+    N, D, M = prob.N, prob.D, prob.M
+    sc = np.abs(W.reshape(M, -1)).max(axis=1)
+    sc[N:N + D] = max(sc[N:N + D].max(), W[:N].sum(axis=0).max() * cmax)
+    sc[N + D + 1:] = 1.0
+    err = (np.abs(got - W).reshape(M, -1).max(axis=1) / sc).max()
+    print(f"config3 256^3: {K} steps, max rel {err:.2e}")
+    assert err <= K * 1e-11
+
+
 def test_advance_past_t_end(H, orc):
     """Steps past t_end: the device time stops at t_end, the later steps
     take dt = 0, and K steps in one call equal K single steps."""

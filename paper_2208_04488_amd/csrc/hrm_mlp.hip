@@ -234,18 +234,32 @@ __global__ void __launch_bounds__(TR_BLOCK) k_mlp_grad(const GradArgs A)
     }
 }
 
-// fixed-order sum of the workgroup partials (double accumulation)
-__global__ void __launch_bounds__(256) k_mlp_reduce(const float* partial, int nblk, int count, float* grad,
-                                                    float* loss)
+// fixed-order sum of the workgroup partials (double accumulation): a
+// workgroup takes RD_P entries, RD_S threads per entry each sum every RD_S-th
+// partial in order, then the RD_S sums are added in order
+constexpr int RD_P = 16, RD_S = 16;
+__global__ void __launch_bounds__(RD_P* RD_S) k_mlp_reduce(const float* partial, int nblk, int count, float* grad,
+                                                          float* loss)
 {
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= TR_PARTIAL) return;
+    __shared__ double sh[RD_S][RD_P];
+    const int pl = threadIdx.x % RD_P, part = threadIdx.x / RD_P;
+    const int p = blockIdx.x * RD_P + pl;
     double acc = 0.0;
-    for (int b = 0; b < nblk; ++b) acc += (double)partial[(size_t)b * TR_PARTIAL + p];
-    if (p < MLP_NPARAM)
-        grad[p] = (float)acc;
-    else
-        *loss = (float)(acc / count);
+    if (p < TR_PARTIAL) {
+#pragma unroll 8
+        for (int b = part; b < nblk; b += RD_S) acc += (double)partial[(size_t)b * TR_PARTIAL + p];
+    }
+    sh[part][pl] = acc;
+    __syncthreads();
+    if (part == 0 && p < TR_PARTIAL) {
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < RD_S; ++k) sum += sh[k][pl];
+        if (p < MLP_NPARAM)
+            grad[p] = (float)sum;
+        else
+            *loss = (float)(sum / count);
+    }
 }
 
 __global__ void __launch_bounds__(256) k_mlp_adam(float* P, const float* g, float* m, float* v, float lr, float b1,
@@ -351,8 +365,8 @@ int hrm_mlp_grad(const float* d_params, const float* d_X, const float* d_T, long
     const int nblk = (count + hrm::TR_BLOCK - 1) / hrm::TR_BLOCK;
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(hrm::k_mlp_grad, dim3(nblk), dim3(hrm::TR_BLOCK), 0, s, A);
-    hipLaunchKernelGGL(hrm::k_mlp_reduce, dim3((hrm::TR_PARTIAL + 255) / 256), dim3(256), 0, s, d_work, nblk, count,
-                       d_grad, d_loss);
+    hipLaunchKernelGGL(hrm::k_mlp_reduce, dim3((hrm::TR_PARTIAL + hrm::RD_P - 1) / hrm::RD_P),
+                       dim3(hrm::RD_P * hrm::RD_S), 0, s, d_work, nblk, count, d_grad, d_loss);
     return hipGetLastError() == hipSuccess ? HRM_OK : HRM_EDEVICE;
 }
 

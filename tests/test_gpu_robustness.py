@@ -104,6 +104,44 @@ def test_extreme_shock_tube(H):
     assert failed(toff, doff)
 
 
+def test_flux_blending_app_b(H):
+    """App. B: the extreme shock tube at 1000 points with and without the
+    flux and velocity blending.  Both stay admissible; the density and
+    velocity barely change (the paper's finding); the pressure error against
+    the exact solution is lower with the blending, and the pressure varies
+    less across the material interface with it."""
+    import oracle
+    from oracle import exact_riemann as ER
+    oracle.build(force=False)
+    R = H.FUSE_RELAX
+    res = {}
+    for name, flags in (("blend", R), ("no_blend", R | H.NO_BLEND)):
+        l1, W, t, d = extreme_shock_tube_l1(H, 1000, 8e-9, flags)
+        assert t == pytest.approx(1e-5, rel=1e-12) and d["relax_bad"] == 0 and admissible(W, 2, 1)
+        prob = I.shock_tube(1000, extreme=True)
+        o = oracle.from_problem(prob)
+        p = np.array([o.prim(W[:, i])["p"] for i in range(W.shape[1])])
+        eos = prob.eos
+        L = dict(rho=1000.0, u=0.0, p=1e12, gamma=eos.gamma[0], pinf=eos.pinf[0])
+        Rs = dict(rho=20.0, u=0.0, p=1e5, gamma=eos.gamma[1], pinf=0.0)
+        x = prob.centres(0)
+        rex, uex, pex = ER.solve(x, t, 0.8, L, Rs)
+        dx = prob.dx[0]
+        ppost = pex[np.where(pex > 2e5)[0].max() - 2]  # post-shock pressure in the gas
+        ic = int(np.argmin(np.abs(W[4] - 0.5)))          # the material interface
+        near = slice(ic - 15, ic + 16)
+        res[name] = dict(rho=l1, u=float(np.abs(W[2] / (W[0] + W[1]) - uex).sum() * dx),
+                         p=float(np.abs(p - pex).sum() * dx / ppost),
+                         tv=float(np.abs(np.diff(p[near])).sum() / ppost))
+    print("App. B, L1 against the exact solution (p relative to the post-shock pressure) and the pressure "
+          "variation across the interface:", res)
+    b, nb = res["blend"], res["no_blend"]
+    assert abs(b["rho"] - nb["rho"]) <= 0.1 * nb["rho"]
+    assert abs(b["u"] - nb["u"]) <= 0.1 * nb["u"]
+    assert b["p"] < nb["p"]
+    assert b["tv"] < nb["tv"]
+
+
 # ------------------------------------------------------------------ Sec. 5.6
 def run_shock_interface(H, n, dt, flags):
     prob = I.shock_interface(n)

@@ -1,0 +1,96 @@
+"""A stage past 2^31 state values: the 1024 x 512 liquid column tiled 26 x 26
+on the device (26 624 x 13 312 cells, 354 M cells x 8 components = 2.8e9
+doubles, so component offsets c * ncell + cell pass 2^31; 113 GB of device
+memory with the library's buffers).  The wavespeed, the time step and one
+SSP-RK3 stage with the relaxation run through the C ABI; sampled cells are
+compared with the oracle run on their 7 x 7 neighbourhood (a cell's update
+depends on nodes at most 3 away along each axis) at the GPU's time step.
+"""
+import numpy as np
+import pytest
+
+from paper_2208_04488_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+REPS = 26
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2208_04488_amd import hrm
+    return hrm
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+def test_stage_past_2_31_values(H, orc):
+    import torch
+    base = I.config2(1024, 512)
+    N, D, M = base.N, base.D, base.M
+    bny, bnx = 512, 1024
+    ny, nx = bny * REPS, bnx * REPS
+    assert (M - 1) * ny * nx > 2 ** 31
+    e = base.eos
+    ob = orc.from_problem(base)
+    cmax = ob.max_wavespeed(base.W)
+    g = H.make_grid(2, (nx, ny), base.dx, base.bc, flags=H.FUSE_RELAX)
+    ctx = H.hrm_create(g, H.make_eos(e.gamma, e.cv, e.pinf, e.q), None)
+    try:
+        W = torch.from_numpy(base.W).cuda().repeat(1, 1, REPS, REPS)
+        maxs = torch.zeros(4, dtype=torch.float64, device="cuda")
+        slot = torch.zeros(8, dtype=torch.float64, device="cuda")
+        H.hrm_max_wavespeed(ctx, W, maxs)
+        H.hrm_compute_dt(ctx, maxs, base.cfl, 0.0, 0.0, slot)
+        out = torch.empty_like(W)
+        H.hrm_rk_stage(ctx, 0, W, W, out, slot)
+        torch.cuda.synchronize()
+        ms = maxs[:D].cpu().numpy()
+        assert np.allclose(ms, cmax, rtol=1e-13, atol=0), (ms, cmax)
+        sl = slot.cpu().numpy()
+        dt, lam = float(sl[0]), [float(sl[1]), float(sl[2])]
+        scale = np.abs(base.W.reshape(M, -1)).max(axis=1)
+        scale[N:N + D] = max(scale[N:N + D].max(), base.W[:N].sum(axis=0).max() * cmax.max())
+        scale[N + D + 1:] = 1.0
+        rng = np.random.default_rng(2718)
+        # domain corners and edges
+        cells = [(0, 0), (0, nx - 1), (ny - 1, 0), (ny - 1, nx - 1), (ny // 2, 0), (0, nx // 2),
+                 (ny - 1, nx // 2 + 7), (ny // 2 + 3, nx - 1)]
+        # in tiles near the start, the middle and the end of the arrays, on the centre row: the
+        # shock (x = 358), the column's edge (410, 614), the bubble's edge (481, 543) and the seam
+        # between two tiles (post-shock air next to the ambient air of the tile before)
+        for ty, tx in ((0, 0), (13, 12), (25, 25)):
+            yc = ty * bny + bny // 2
+            cells += [(yc, tx * bnx + xo) for xo in (358, 410, 481, 543, 614)]
+            if tx > 0:
+                cells += [(yc, tx * bnx - 1), (yc, tx * bnx)]
+        cells += [(int(y), int(x)) for y, x in zip(rng.integers(0, ny, 8), rng.integers(0, nx, 8))]
+        worst, moved = 0.0, 0
+        for y, x in cells:
+            y0, y1, x0, x1 = max(y - 3, 0), min(y + 4, ny), max(x - 3, 0), min(x + 4, nx)
+            Wp = W[:, :, y0:y1, x0:x1].cpu().numpy().copy()
+            o = orc.Oracle(N, 2, (x1 - x0, y1 - y0), base.dx, base.bc, e.gamma, e.cv, e.pinf, e.q)
+            ref = o.stage(0, Wp, Wp, dt, lam)[:, 0, y - y0, x - x0]
+            got = out[:, 0, y, x].cpu().numpy()
+            err = float((np.abs(got - ref) / scale).max())
+            worst = max(worst, err)
+            assert err <= TOL, ((y, x), err)
+            moved += bool((np.abs(got - Wp[:, 0, y - y0, x - x0]) / scale).max() > 1e-6)
+        print(f"{nx} x {ny}: {len(cells)} sampled cells, {moved} of them changed by the stage, "
+              f"max rel {worst:.2e}")
+        # the shock cells and the seams move; the material interfaces are at
+        # rest in pressure equilibrium, so their update is zero to round-off
+        assert moved >= 6
+        assert torch.isfinite(out).all()
+        del W, out
+    finally:
+        H.hrm_destroy(ctx)
+        torch.cuda.empty_cache()

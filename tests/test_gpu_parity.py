@@ -82,8 +82,14 @@ def check_stages(H, orc, prob, W0, flags=0, relax=True, tol=TOL, counters=True, 
     if counters:
         dg = s.diagnostics()
         co = o.counter_dict()
+        env = counter_envelope(orc, prob, W0, dt, lam, flags, relax, params) if counters == "envelope" else None
         for key in ("alg1", "alg2", "interp_hs", "alg3", "alg4", "flux_hs", "relax_bad"):
-            if counters == "flips":
+            if env is not None:
+                # few faces, every one at an extreme jump: the counts move in
+                # steps when an input moves by one ulp, so they must lie in the
+                # range the oracle itself gives over such perturbations
+                assert env[key][0] <= dg[key] <= env[key][1], (key, dg[key], env[key])
+            elif counters == "flips":
                 # adversarial inputs: trace partial densities at extreme jumps
                 # are small differences of large characteristic values, so the
                 # 1e-10 threshold tests can flip on last-bit differences; both
@@ -94,6 +100,23 @@ def check_stages(H, orc, prob, W0, flags=0, relax=True, tol=TOL, counters=True, 
                 assert dg[key] == co[key], (key, dg[key], co[key])
     s.close()
     return o.counter_dict()
+
+
+def counter_envelope(orc, prob, W0, dt, lam, flags, relax, params, trials=16):
+    """Range of the oracle's limiter counters over the three stages of
+    check_stages when every input value moves by at most one ulp."""
+    rng = np.random.default_rng(99)
+    env = None
+    for t in range(trials + 1):
+        Wp = W0 if t == 0 else W0 * (1.0 + rng.choice([-1.0, 0.0, 1.0], W0.shape) * 2.0 ** -52)
+        o = orc.from_problem(prob, flags=flags & SCHEME, **(params or {}))
+        Ws = Wp
+        for k in range(3):
+            Ws = o.stage(k, Wp, Ws, dt, lam, relax=relax)
+        c = o.counter_dict()
+        env = {k: (v, v) for k, v in c.items()} if env is None else \
+            {k: (min(env[k][0], c[k]), max(env[k][1], c[k])) for k in c}
+    return env
 
 
 def developed(orc, prob, steps, flags=0):
@@ -193,7 +216,7 @@ def test_stage_parity_without_relaxation(H, orc):
     check_stages(H, orc, prob, developed(orc, prob, 2), relax=False)
 
 
-def rough_problem(D, n, seed):
+def rough_problem(D, n, seed, bc=0):
     """Every cell an independent admissible state: jumps everywhere, so the
     limiters and hard switches fire on many faces."""
     eos = I.eos_of(I.LIQ_B, I.AIR, I.HELIUM)
@@ -202,7 +225,7 @@ def rough_problem(D, n, seed):
     nn = tuple(n) + (1,) * (3 - D)
     W = W.reshape((W.shape[0], nn[2], nn[1], nn[0]))
     dx = tuple(1e-3 for _ in range(D))
-    return I.Problem("rough", eos, D, tuple(n), dx, [(0, 0)] * D, np.ascontiguousarray(W))
+    return I.Problem("rough", eos, D, tuple(n), dx, [(bc, bc)] * D, np.ascontiguousarray(W))
 
 
 @pytest.mark.parametrize("D,n", [(1, (300,)), (2, (40, 33)), (3, (12, 11, 10))])
@@ -211,6 +234,16 @@ def test_stage_parity_rough(H, orc, D, n):
     cnt = check_stages(H, orc, prob, prob.W, counters="flips")
     assert cnt["alg1"] + cnt["alg2"] + cnt["interp_hs"] > 0
     assert cnt["alg3"] > 0
+
+
+# degenerate and just-past-a-tile extents in 2D and 3D (x tiles hold 63 cells,
+# y and z tiles 15), transmissive and periodic
+@pytest.mark.parametrize("n,bc", [((1, 1), 0), ((1, 1), 1), ((2, 3), 0), ((3, 1), 1), ((1, 5), 0), ((64, 2), 1),
+                                  ((2, 16), 0), ((3, 17), 1), ((1, 1, 1), 0), ((2, 1, 3), 1), ((3, 16, 2), 0),
+                                  ((2, 2, 16), 1)])
+def test_stage_parity_tiny_grids(H, orc, n, bc):
+    prob = rough_problem(len(n), n, seed=300 + int(np.prod(n)) + bc, bc=bc)
+    check_stages(H, orc, prob, prob.W, counters="envelope")
 
 
 @pytest.mark.parametrize("n,bc", [(1, 0), (2, 0), (3, 0), (5, 0), (3, 1), (4, 1), (7, 1), (255, 0), (256, 1),

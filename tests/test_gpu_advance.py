@@ -32,8 +32,19 @@ def _mlp():
     return learned.init_params(5, last_scale=0.3)
 
 
+def _tiny(n, bc, seed):
+    """Independent random admissible states on a tiny grid (one or two time-step slots)."""
+    eos = I.eos_of(I.LIQ_B, I.AIR, I.HELIUM)
+    D = len(n)
+    W = I.random_admissible(eos, D, int(np.prod(n)), seed=seed, p_range=(1e4, 1e8), u_scale=100.0)
+    nn = tuple(n) + (1,) * (3 - D)
+    W = W.reshape((W.shape[0], nn[2], nn[1], nn[0]))
+    return I.Problem("tiny", eos, D, tuple(n), (1e-3,) * D, [(bc, bc)] * D, np.ascontiguousarray(W))
+
+
 # (problem, flags, precision, learned, steps): ragged tiles in every dimension,
-# Dirichlet sides, the four-equation solver, FP32 faces and learned weights
+# Dirichlet sides, the four-equation solver, FP32 faces, learned weights and
+# grids with one or two slots
 CASES = {
     "config1_364": lambda H: (I.config1(364), 0, H.FP64, False, 6),
     "config2_130x70": lambda H: (I.config2(130, 70), 0, H.FP64, False, 5),
@@ -42,6 +53,9 @@ CASES = {
     "four_eq_shock_tube": lambda H: (I.shock_tube(400), H.FOUR_EQ, H.FP64, False, 8),
     "fp32_config2_96x48": lambda H: (I.config2(96, 48), 0, H.FP32, False, 4),
     "learned_config5_96x48": lambda H: (I.config5(96, 48), 0, H.FP64, True, 4),
+    "tiny_2x3_transmissive": lambda H: (_tiny((2, 3), 0, 11), 0, H.FP64, False, 4),
+    "tiny_1x1x1_periodic": lambda H: (_tiny((1, 1, 1), 1, 12), 0, H.FP64, False, 3),
+    "tiny_5x17_periodic": lambda H: (_tiny((5, 17), 1, 13), 0, H.FP64, False, 4),
 }
 
 

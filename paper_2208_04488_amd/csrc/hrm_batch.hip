@@ -124,6 +124,8 @@ __global__ void __launch_bounds__(BS, 3) k_batch(const BatchArgs A)
                     const EosDev& e = A.e;
                     const ParDev& P = A.P;
                     // stage the tile c0-3 .. c0+BS+1 with its primitives
+                    // (at raised priority, as in k_sweep)
+                    __builtin_amdgcn_s_setprio(3);
                     for (int l = ts; l < LN; l += BS) {
                         const int g = map_bc(c0 - 3 + l, n, HRM_BC_TRANSMISSIVE, HRM_BC_TRANSMISSIVE);
                         double W[M];
@@ -139,6 +141,7 @@ __global__ void __launch_bounds__(BS, 3) k_batch(const BatchArgs A)
                         lds[F::C * FS + l] = s.c;
                         lds[F::RC2 * FS + l] = s.rc2;
                     }
+                    __builtin_amdgcn_s_setprio(0);
                     __syncthreads();
                     double G[M], Gp[NA];
                     {

@@ -133,6 +133,9 @@ void hrm_default_params(hrm_params* p);
  * library's scratch on the current device: one M x ncell right-hand-side
  * buffer (dim > 1), two M x ncell stage buffers for hrm_advance, wavespeed
  * partials and the counters.  `params` NULL means hrm_default_params().
+ * HRM_EUNSUPPORTED if a sweep launch would exceed the device's grid limits:
+ * in 2D n[0] <= 4 128 705 and n[1] <= 983 025, in 3D also n[1] and n[2]
+ * <= 65 535 (1D lines have no such limit).
  * On failure *out is NULL and the code says why (no message store exists). */
 int hrm_create(const hrm_grid* grid, const hrm_eos* eos, const hrm_params* params, hrm_ctx** out);
 

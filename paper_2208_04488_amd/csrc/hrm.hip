@@ -87,6 +87,11 @@ __device__ inline unsigned long long wave_umax64(unsigned long long v)
 // across it.  DIR == 0: blockDim = (BS, BA), across = y, blockIdx.z = z.
 // DIR == 1: blockDim = (BA, BS), across = x, blockIdx.z = z.
 // DIR == 2: blockDim = (BA, BS), across = x, blockIdx.y = y.
+// The tile index along the sweep is blockIdx.y (DIR 0 in 2D and 3D, DIR 1)
+// or blockIdx.z (DIR 2), so that tiles sharing a halo have linear block
+// indices a multiple of gridDim.x apart and land on the same XCD (and L2)
+// when gridDim.x is a multiple of 8; 1D keeps the tiles on blockIdx.x, the
+// dimension with room for long lines.
 // The register budget of the sweeps is cut to three waves per SIMD (168
 // VGPRs).  For three species that spills ~200 bytes per lane, mostly around
 // the characteristic back-projection, but the third wave hides more LDS and
@@ -116,8 +121,8 @@ __global__ void __launch_bounds__(BS* BA, SWEEP_WAVES) k_sweep(const SweepArgs A
     const long long st[3] = {1, A.n[0], (long long)A.n[0] * A.n[1]};
     int c0, abase, other, adim, odim;
     if (DIR == 0) {
-        c0 = blockIdx.x * (BS - 1);
-        abase = blockIdx.y * BA;
+        c0 = (D == 1 ? blockIdx.x : blockIdx.y) * (BS - 1);
+        abase = (D == 1 ? blockIdx.y : blockIdx.x) * BA;
         other = blockIdx.z;
         adim = 1;
         odim = 2;
@@ -554,7 +559,8 @@ void sweep_tile(int D, int dir, int& BS, int& BA)
 dim3 sweep_grid(const hrm_ctx* c, int dir, int BS, int BA)
 {
     const int cells = BS - 1;
-    if (dir == 0) return dim3((c->n[0] + cells - 1) / cells, (c->n[1] + BA - 1) / BA, c->n[2]);
+    if (dir == 0 && c->D == 1) return dim3((c->n[0] + cells - 1) / cells, (c->n[1] + BA - 1) / BA, c->n[2]);
+    if (dir == 0) return dim3((c->n[1] + BA - 1) / BA, (c->n[0] + cells - 1) / cells, c->n[2]);
     if (dir == 1) return dim3((c->n[0] + BA - 1) / BA, (c->n[1] + cells - 1) / cells, c->n[2]);
     return dim3((c->n[0] + BA - 1) / BA, c->n[1], (c->n[2] + cells - 1) / cells);
 }
@@ -852,6 +858,16 @@ int hrm_create(const hrm_grid* g, const hrm_eos* e, const hrm_params* prm, hrm_c
     if (!((c->N == 2 || c->N == 3))) {
         delete c;
         return HRM_EUNSUPPORTED;
+    }
+    for (int d = 0; d < c->D; ++d) {
+        // every sweep launch within the grid limits (y and z at most 65535 blocks)
+        int BS, BA;
+        sweep_tile(c->D, d, BS, BA);
+        const dim3 gd = sweep_grid(c, d, BS, BA);
+        if (gd.y > 65535u || gd.z > 65535u) {
+            delete c;
+            return HRM_EUNSUPPORTED;
+        }
     }
     for (int k = 0; k < hrm::MAXN; ++k) {
         const bool on = k < c->N;

@@ -64,6 +64,17 @@ def test_create_rejects_bad_input(H, case):
     assert ctx.value is None
 
 
+@pytest.mark.parametrize("dim,n", [(2, (4_128_706, 1)), (2, (1, 983_026)), (3, (1, 65_536, 1)), (3, (1, 1, 65_536))])
+def test_create_rejects_grids_past_the_launch_limits(H, dim, n):
+    """A sweep's tile and line indices ride on grid dimensions limited to
+    65 535 blocks; such grids are refused before any device call."""
+    g = H.make_grid(dim, n, (0.1,) * dim, [(0, 0)] * dim)
+    ctx = ctypes.c_void_p(123)
+    rc = H.lib.hrm_create(ctypes.byref(g), ctypes.byref(_eos(H)), None, ctypes.byref(ctx))
+    assert rc == H.HRM_EUNSUPPORTED
+    assert ctx.value is None
+
+
 def test_null_context_is_rejected(H):
     assert H.lib.hrm_relax(None, None, None) == H.HRM_EINVAL
     assert H.lib.hrm_rk_stage(None, 0, None, None, None, None, None) == H.HRM_EINVAL

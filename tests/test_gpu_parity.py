@@ -166,6 +166,47 @@ def test_relax_leaves_inadmissible_cells(H, orc):
     s.close()
 
 
+def test_injected_inadmissible_cells_are_reported(H, orc):
+    """Failure injection: cells with rho e-tilde < 0, a non-finite energy, a
+    negative partial density and a volume fraction above one written into an
+    admissible 2D state.  The relaxation rejects exactly the cells the
+    oracle's does (leaving them unchanged) and hrm_get_diagnostics returns
+    HRM_EADMISSIBLE; a fused stage from the same state reports it too; a
+    reset clears it."""
+    import torch
+    eos = I.eos_of(I.LIQ_B, I.AIR, I.HELIUM)
+    N, D, nx, ny = 3, 2, 16, 12
+    W = I.random_admissible(eos, D, nx * ny, seed=21).reshape(2 * N + D, 1, ny, nx)
+    E = N + D
+    qbar = sum(W[k] * eos.q[k] for k in range(N))
+    W[E, 0, 2, 3] = qbar[0, 2, 3] - 10.0
+    W[E, 0, 5, 7] = np.nan
+    W[0, 0, 8, 1] = -1e-3 * abs(W[0, 0, 8, 1]) - 1e-6
+    W[E + 1, 0, 10, 12] = 1.5
+    prob = I.Problem("inject", eos, D, (nx, ny), (1e-3, 1e-3), [(0, 0)] * D, W)
+    o = orc.from_problem(prob)
+    o.relax(W)
+    nbad = o.counter_dict()["relax_bad"]
+    assert nbad >= 2
+    s = solver(H, prob, H.FUSE_RELAX)
+    s.relax()
+    d = s.diagnostics()
+    got = s.state()
+    assert d["relax_bad"] == nbad and d["status"] == H.HRM_EADMISSIBLE
+    for y, x in ((2, 3), (5, 7)):
+        assert np.array_equal(got[:, 0, y, x], W[:, 0, y, x], equal_nan=True)
+    H.hrm_reset_diagnostics(s.ctx)
+    d = s.diagnostics()
+    assert d["relax_bad"] == 0 and d["status"] == H.HRM_OK
+    s.set_state(W)
+    s.set_slot(1e-9, [1e-9 / 1e-3, 1e-9 / 1e-3])
+    s.stage(0, s.W, s.W)
+    torch.cuda.synchronize()
+    d = s.diagnostics()
+    assert d["relax_bad"] >= nbad and d["status"] == H.HRM_EADMISSIBLE
+    s.close()
+
+
 @pytest.mark.parametrize("maker", ["config1", "shock_tube_extreme", "advection_2d", "config2_small", "config3_small"])
 def test_wavespeed_and_dt_parity(H, orc, maker):
     prob = {"config1": lambda: I.config1(400), "shock_tube_extreme": lambda: I.shock_tube(1000, True),

@@ -86,12 +86,12 @@ __device__ inline unsigned long long wave_umax64(unsigned long long v)
 // Tile: BS face threads along the sweep direction (BS-1 cells), BA threads
 // across it.  DIR == 0: blockDim = (BS, BA), across = y, blockIdx.z = z.
 // DIR == 1: blockDim = (BA, BS), across = x, blockIdx.z = z.
-// DIR == 2: blockDim = (BA, BS), across = x, blockIdx.y = y.
-// The tile index along the sweep is blockIdx.y (DIR 0 in 2D and 3D, DIR 1)
-// or blockIdx.z (DIR 2), so that tiles sharing a halo have linear block
-// indices a multiple of gridDim.x apart and land on the same XCD (and L2)
-// when gridDim.x is a multiple of 8; 1D keeps the tiles on blockIdx.x, the
-// dimension with room for long lines.
+// DIR == 2: blockDim = (BA, BS), across = x, blockIdx.z = y.
+// The tile index along the sweep is blockIdx.y (in 2D and 3D), so that
+// tiles sharing a halo have linear block indices gridDim.x apart: on the
+// same XCD (and L2) when gridDim.x is a multiple of 8, and dispatched close
+// together; 1D keeps the tiles on blockIdx.x, the dimension with room for
+// long lines.
 // The register budget of the sweeps is cut to three waves per SIMD (168
 // VGPRs).  For three species that spills ~200 bytes per lane, mostly around
 // the characteristic back-projection, but the third wave hides more LDS and
@@ -133,9 +133,9 @@ __global__ void __launch_bounds__(BS* BA, SWEEP_WAVES) k_sweep(const SweepArgs A
         adim = 0;
         odim = 2;
     } else {
-        c0 = blockIdx.z * (BS - 1);
+        c0 = blockIdx.y * (BS - 1);
         abase = blockIdx.x * BA;
-        other = blockIdx.y;
+        other = blockIdx.z;
         adim = 0;
         odim = 1;
     }
@@ -562,7 +562,7 @@ dim3 sweep_grid(const hrm_ctx* c, int dir, int BS, int BA)
     if (dir == 0 && c->D == 1) return dim3((c->n[0] + cells - 1) / cells, (c->n[1] + BA - 1) / BA, c->n[2]);
     if (dir == 0) return dim3((c->n[1] + BA - 1) / BA, (c->n[0] + cells - 1) / cells, c->n[2]);
     if (dir == 1) return dim3((c->n[0] + BA - 1) / BA, (c->n[1] + cells - 1) / cells, c->n[2]);
-    return dim3((c->n[0] + BA - 1) / BA, c->n[1], (c->n[2] + cells - 1) / cells);
+    return dim3((c->n[0] + BA - 1) / BA, (c->n[2] + cells - 1) / cells, c->n[1]);
 }
 
 template <int N, int D>

@@ -34,6 +34,9 @@ def orc():
 
 def test_stage_past_2_31_values(H, orc):
     import torch
+    free, _ = torch.cuda.mem_get_info()
+    if free < 120 * 2 ** 30:
+        pytest.skip(f"needs 120 GiB of free device memory, {free / 2 ** 30:.0f} GiB free")
     base = I.config2(1024, 512)
     N, D, M = base.N, base.D, base.M
     bny, bnx = 512, 1024

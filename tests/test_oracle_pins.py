@@ -616,6 +616,200 @@ def test_flux_limiter_properties():
     assert np.array_equal(Gm, Gm_lo) and np.array_equal(Gp, Gp_lo)
 
 
+# Exact pins of Alg. 3, Alg. 4 and the flux hard switch (Sec. 4.3.2).  Each
+# case builds a face between two admissible nodes at rest, takes the
+# first-order HLLC pair as the reference and perturbs one slot of the
+# high-order pair so that exactly one half-cell quantity misses its bound.
+# The paper fixes where the limited half-cell state must land: theta solves
+# (1 - theta) a + theta b = min(eps, a), with a the first-order value, and one
+# theta scales the whole flux pair, both sides.  These fail if theta is set to
+# 0 on any violation, if eps^HS stands in for eps, or if theta is taken per side.
+
+def _face_setup(eos, alphas_L, alphas_R, pL, pR, T):
+    D = 1
+    o = oracle_for(eos)
+    L = I.equilibrium_state(eos, [np.array(a) for a in alphas_L], [np.array(0.0)], pL, T).ravel()
+    R = I.equilibrium_state(eos, [np.array(a) for a in alphas_R], [np.array(0.0)], pR, T).ravel()
+    N = eos.N
+    IA = N + D + 1
+    Glo, ss = o.hllc(0, L, R)
+    Gm_lo, Gp_lo = Glo.copy(), Glo.copy()
+    Gm_lo[IA:] -= ss * L[IA:]
+    Gp_lo[IA:] -= ss * R[IA:]
+    return o, L, R, Gm_lo, Gp_lo
+
+
+def _half_cell(o, L, R, lam, Gm, Gp):
+    """W_i^+ = W_i - 2 lam (G^- - F_i), W_{i+1}^- = W_{i+1} + 2 lam (G^+ - F_{i+1});
+    F has zero volume-fraction slots (Sec. 4.3.2)."""
+    N, D = o.N, o.D
+    def F(w):
+        pr = o.prim(w)
+        f = np.zeros(o.M)
+        u = pr["u"][0]
+        f[:N] = w[:N] * u
+        f[N] = w[N] * u + pr["p"]
+        f[N + D] = (w[N + D] + pr["p"]) * u
+        return f
+    return L - 2 * lam * (Gm - F(L)), R + 2 * lam * (Gp - F(R))
+
+
+def _alphas(w, N, D):
+    a = list(w[N + D + 1:])
+    return np.array(a + [1.0 - sum(a)])
+
+
+def _common_theta(Gm, Gp, Gm_lo, Gp_lo, Gm_ho, Gp_ho):
+    """The single theta with G = G_lo + theta (G_ho - G_lo) in every slot of both
+    vectors; asserts that one exists."""
+    th = None
+    for G, lo, ho in ((Gm, Gm_lo, Gm_ho), (Gp, Gp_lo, Gp_ho)):
+        for c in range(G.size):
+            d = ho[c] - lo[c]
+            if d == 0:
+                assert G[c] == lo[c]
+                continue
+            t = (G[c] - lo[c]) / d
+            if th is None:
+                th = t
+            assert t == pytest.approx(th, rel=1e-9, abs=1e-12), (c, t, th)
+    return th
+
+
+LAM = 0.4 / 3000.0
+
+
+def test_alg3_partial_density_lands_on_eps():
+    """A trace partial density of W_i^+ dips below min(eps, a): the limited value
+    is eps = 1e-10 (a = 1.2e-8), and the same theta scales G^+ although
+    W_{i+1}^- satisfies every bound."""
+    eos = I.table1_eos()
+    o, L, R, Gm_lo, Gp_lo = _face_setup(eos, [1 - 1e-8, 1e-8], [0.4, 0.6], 1e5, 1e5, 300.0)
+    Wp_lo, Wm_lo = _half_cell(o, L, R, LAM, Gm_lo, Gp_lo)
+    a = Wp_lo[1]
+    assert a > 1e-10
+    Gm_ho, Gp_ho = Gm_lo.copy(), Gp_lo.copy()
+    Gm_ho[1] += (a + 3e-8) / (2 * LAM)      # W_i^+ alpha_2 rho_2 -> -3e-8
+    Gp_ho[0] += 0.05 * Wm_lo[0] / (2 * LAM)  # harmless on the - side of i+1
+    o.counters[:] = 0
+    Gm, Gp = o.flux_limit(0, L, R, LAM, Gm_ho, Gp_ho, Gm_lo, Gp_lo)
+    Wp, Wm = _half_cell(o, L, R, LAM, Gm, Gp)
+    assert Wp[1] == pytest.approx(1e-10, rel=1e-6)
+    th = _common_theta(Gm, Gp, Gm_lo, Gp_lo, Gm_ho, Gp_ho)
+    assert 0 < th < 1
+    assert Gp[0] != Gp_ho[0]  # theta reached the other side
+    c = o.counter_dict()
+    assert (c["alg3"], c["alg4"], c["flux_hs"]) == (1, 0, 0)
+
+
+def test_alg3_partial_density_below_eps_keeps_first_order_value():
+    """When the first-order value a is itself below eps, the bound is a:
+    theta = 0 and the limited pair is the first-order one (no hard switch)."""
+    eos = I.table1_eos()
+    o, L, R, Gm_lo, Gp_lo = _face_setup(eos, [1 - 1e-13, 1e-13], [0.4, 0.6], 1e5, 1e5, 300.0)
+    Wp_lo, _ = _half_cell(o, L, R, LAM, Gm_lo, Gp_lo)
+    assert 0 < Wp_lo[1] < 1e-11
+    Gm_ho, Gp_ho = Gm_lo.copy(), Gp_lo.copy()
+    Gm_ho[1] += (Wp_lo[1] + 1e-12) / (2 * LAM)
+    o.counters[:] = 0
+    Gm, Gp = o.flux_limit(0, L, R, LAM, Gm_ho, Gp_ho, Gm_lo, Gp_lo)
+    assert np.array_equal(Gm, Gm_lo) and np.array_equal(Gp, Gp_lo)
+    c = o.counter_dict()
+    assert (c["alg3"], c["flux_hs"]) == (1, 0)
+
+
+def test_alg3_derived_volume_fraction_on_the_right_side():
+    """Three species: the derived alpha_3 = 1 - alpha_1 - alpha_2 of W_{i+1}^-
+    dips below min(eps, a); it lands on eps and the same theta scales G^-."""
+    eos = I.eos_of(I.LIQ_B, I.AIR, I.HELIUM)
+    N, D = 3, 1
+    IA = N + D + 1
+    o, L, R, Gm_lo, Gp_lo = _face_setup(eos, [0.2, 0.5, 0.3], [1e-8, 1 - 2e-8, 1e-8], 1e5, 1e5, 300.0)
+    _, Wm_lo = _half_cell(o, L, R, LAM, Gm_lo, Gp_lo)
+    a = _alphas(Wm_lo, N, D)[2]
+    assert a > 1e-10
+    Gm_ho, Gp_ho = Gm_lo.copy(), Gp_lo.copy()
+    Gp_ho[IA + 1] += (a + 2e-7) / (2 * LAM)       # alpha_2 of W_{i+1}^- up, alpha_3 -> -2e-7
+    Gm_ho[N] += 1e-3 * abs(Gm_lo[N]) + 1.0          # momentum on the other side
+    o.counters[:] = 0
+    Gm, Gp = o.flux_limit(0, L, R, LAM, Gm_ho, Gp_ho, Gm_lo, Gp_lo)
+    _, Wm = _half_cell(o, L, R, LAM, Gm, Gp)
+    assert _alphas(Wm, N, D)[2] == pytest.approx(1e-10, rel=1e-5)
+    th = _common_theta(Gm, Gp, Gm_lo, Gp_lo, Gm_ho, Gp_ho)
+    assert 0 < th < 1 and Gm[N] != Gm_ho[N]
+    c = o.counter_dict()
+    assert (c["alg3"], c["alg4"], c["flux_hs"]) == (1, 0, 0)
+
+
+def test_alg4_internal_energy_lands_on_eps():
+    """Only the energy slot differs between the pairs, so rho e-tilde is linear
+    along the blend and Alg. 4's theta puts rho e-tilde of W_i^+ exactly on
+    min(eps, a) = 1e-8 (a low-pressure gas keeps the round-off far below it);
+    the same theta scales the energy slot of G^+."""
+    eos = I.table1_eos()
+    N, D = 2, 1
+    IE = N + D
+    o, L, R, Gm_lo, Gp_lo = _face_setup(eos, [1e-8, 1 - 1e-8], [1e-8, 1 - 1e-8], 1.0, 1.0, 300.0)
+    Wp_lo, Wm_lo = _half_cell(o, L, R, LAM, Gm_lo, Gp_lo)
+    a = o.prim(Wp_lo)["rhoe_t"]
+    assert 1e-8 < a < 100
+    Gm_ho, Gp_ho = Gm_lo.copy(), Gp_lo.copy()
+    Gm_ho[IE] += (a + 5.0) / (2 * LAM)         # rho e-tilde of W_i^+ -> -5
+    Gp_ho[IE] += 0.1 * a / (2 * LAM)           # W_{i+1}^- stays admissible
+    o.counters[:] = 0
+    Gm, Gp = o.flux_limit(0, L, R, LAM, Gm_ho, Gp_ho, Gm_lo, Gp_lo)
+    Wp, Wm = _half_cell(o, L, R, LAM, Gm, Gp)
+    assert o.prim(Wp)["rhoe_t"] == pytest.approx(1e-8, rel=1e-5)
+    th = _common_theta(Gm, Gp, Gm_lo, Gp_lo, Gm_ho, Gp_ho)
+    assert 0 < th < 1 and Gp[IE] != Gp_ho[IE]
+    c = o.counter_dict()
+    assert (c["alg3"], c["alg4"], c["flux_hs"]) == (0, 1, 0)
+
+
+def test_alg4_nonlinear_path_stays_above_the_bound():
+    """With momentum in the blend rho e-tilde is concave along it (Lemma 1), so
+    the value-interpolated theta of Alg. 4 leaves rho e-tilde at or above
+    min(eps, a) without reaching the first-order value."""
+    eos = I.table1_eos()
+    N, D = 2, 1
+    o, L, R, Gm_lo, Gp_lo = _face_setup(eos, [1e-8, 1 - 1e-8], [1e-8, 1 - 1e-8], 1.0, 1.0, 300.0)
+    Wp_lo, _ = _half_cell(o, L, R, LAM, Gm_lo, Gp_lo)
+    a = o.prim(Wp_lo)["rhoe_t"]
+    rho = Wp_lo[:N].sum()
+    Gm_ho = Gm_lo.copy()
+    Gm_ho[N] -= 3.0 * np.sqrt(2 * a * rho) / (2 * LAM)  # kinetic energy 9 a: rho e-tilde < 0
+    o.counters[:] = 0
+    Gm, Gp = o.flux_limit(0, L, R, LAM, Gm_ho, Gp_lo.copy(), Gm_lo, Gp_lo)
+    Wp, _ = _half_cell(o, L, R, LAM, Gm, Gp)
+    re = o.prim(Wp)["rhoe_t"]
+    assert re >= 1e-8 * (1 - 1e-6) and re < a
+    assert not np.array_equal(Gm, Gm_lo)
+    assert o.counter_dict()["alg4"] == 1 and o.counter_dict()["flux_hs"] == 0
+
+
+@pytest.mark.parametrize("eps,hs,fires", [(1e-12, 1e-11, True), (5e-11, 1e-11, False), (5e-11, 1e-10, True)])
+def test_flux_hard_switch_threshold(eps, hs, fires):
+    """The hard switch compares the final half-cell partial density with
+    min(eps^HS, first-order value): with eps below eps^HS the limited value
+    (eps) is below it and the first-order pair is taken whole; otherwise the
+    limited pair stands."""
+    eos = I.table1_eos()
+    o0, L, R, Gm_lo, Gp_lo = _face_setup(eos, [1 - 1e-8, 1e-8], [0.4, 0.6], 1e5, 1e5, 300.0)
+    o = oracle_for(eos, eps_f_ar=eps, hs_f_ar=hs)
+    Wp_lo, _ = _half_cell(o, L, R, LAM, Gm_lo, Gp_lo)
+    Gm_ho, Gp_ho = Gm_lo.copy(), Gp_lo.copy()
+    Gm_ho[1] += (Wp_lo[1] + 3e-8) / (2 * LAM)
+    o.counters[:] = 0
+    Gm, Gp = o.flux_limit(0, L, R, LAM, Gm_ho, Gp_ho, Gm_lo, Gp_lo)
+    Wp, _ = _half_cell(o, L, R, LAM, Gm, Gp)
+    if fires:
+        assert np.array_equal(Gm, Gm_lo) and np.array_equal(Gp, Gp_lo)
+        assert o.counter_dict()["flux_hs"] == 1
+    else:
+        assert Wp[1] == pytest.approx(eps, rel=1e-5)
+        assert o.counter_dict()["flux_hs"] == 0
+
+
 def test_oracle_threads_do_not_change_results(orc):
     pr = I.config2(64, 32)
     o = orc.from_problem(pr)

@@ -253,6 +253,24 @@ int hrm_mlp_grad(const float* d_params, const float* d_X, const float* d_T, long
                  long long stride, int count, float* d_grad, float* d_loss, float* d_work, long long work_floats,
                  void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, training loops that must not allocate, harnesses that forbid
+ * hipMalloc): hrm_mlp_grad without the workspace argument.  The
+ * per-workgroup partial sums go to a fixed array in the library's device
+ * memory, ceil(HRM_MLP_GRAD_NOALLOC_MAX / 64) x 1348 floats (2.8 MB), one copy
+ * per device the library runs on, held until the process ends; its address on
+ * the current device is looked up at the first call there (HRM_EDEVICE if
+ * that fails).  The call allocates nothing and launches the kernels of
+ * hrm_mlp_grad in the same order, so d_grad and d_loss equal hrm_mlp_grad's to
+ * the bit.  count > HRM_MLP_GRAD_NOALLOC_MAX gives HRM_EINVAL (nothing is
+ * launched).  Every entry of the array a call reads is written by that call
+ * first; calls on one device that run at the same time (other streams,
+ * threads or processes' contexts) share the array and race, calls on one
+ * stream are ordered. */
+#define HRM_MLP_GRAD_NOALLOC_MAX 32768
+int hrm_mlp_grad_noalloc(const float* d_params, const float* d_X, const float* d_T, long long nsamp,
+                         long long first, long long stride, int count, float* d_grad, float* d_loss, void* stream);
+
 /* Adam step `step` (>= 1) on the 1347 parameters, all DEVICE floats:
  *   m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
  *   p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps). */

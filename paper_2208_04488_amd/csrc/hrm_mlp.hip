@@ -11,6 +11,7 @@
 
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "hrm.h"
@@ -301,7 +302,67 @@ int extract_launch(const hrm_eos* e, const double* d_W, long long T, int nprob, 
     return hipGetLastError() == hipSuccess ? HRM_OK : HRM_EDEVICE;
 }
 
+// largest minibatch of hrm_mlp_grad_noalloc and the floats of its partials
+constexpr long long NOALLOC_FLOATS =
+    (long long)((HRM_MLP_GRAD_NOALLOC_MAX + TR_BLOCK - 1) / TR_BLOCK) * TR_PARTIAL;
+
 }  // namespace hrm
+
+// The per-workgroup partial sums of hrm_mlp_grad_noalloc: a fixed array in
+// device memory (one copy per device, held until the process ends).  In host
+// code this name is not a device address: kernels get the address that
+// hipGetSymbolAddress returns for the current device (noalloc_scratch).
+static __device__ __align__(256) float scratch[hrm::NOALLOC_FLOATS];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float* g_scratch[MAX_DEVICES] = {};
+
+// address of `scratch` on the current device, looked up once per device
+int noalloc_scratch(float** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) {
+        (void)hipGetLastError();
+        return HRM_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return HRM_EDEVICE;
+        }
+        g_scratch[dev] = static_cast<float*>(p);
+    }
+    *out = g_scratch[dev];
+    return HRM_OK;
+}
+
+// the two launches of a gradient: partials of every workgroup into `work`
+// (each entry written before it is read), then their fixed-order sum
+int grad_launch(const float* d_params, const float* d_X, const float* d_T, long long nsamp, long long first,
+                long long stride, int count, float* d_grad, float* d_loss, float* work, hipStream_t s)
+{
+    hrm::GradArgs A;
+    A.P = d_params;
+    A.X = d_X;
+    A.Tt = d_T;
+    A.nsamp = nsamp;
+    A.first = first % nsamp;
+    A.stride = stride % nsamp == 0 ? 1 : stride % nsamp;
+    A.count = count;
+    A.partial = work;
+    const int nblk = (count + hrm::TR_BLOCK - 1) / hrm::TR_BLOCK;
+    hipLaunchKernelGGL(hrm::k_mlp_grad, dim3(nblk), dim3(hrm::TR_BLOCK), 0, s, A);
+    hipLaunchKernelGGL(hrm::k_mlp_reduce, dim3((hrm::TR_PARTIAL + hrm::RD_P - 1) / hrm::RD_P),
+                       dim3(hrm::RD_P * hrm::RD_S), 0, s, work, nblk, count, d_grad, d_loss);
+    return hipGetLastError() == hipSuccess ? HRM_OK : HRM_EDEVICE;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -353,21 +414,18 @@ int hrm_mlp_grad(const float* d_params, const float* d_X, const float* d_T, long
     if (!d_params || !d_X || !d_T || !d_grad || !d_loss || !d_work) return HRM_EINVAL;
     if (nsamp < 1 || count < 1 || first < 0 || stride < 1) return HRM_EINVAL;
     if (work_floats < hrm_mlp_grad_workspace(count)) return HRM_EINVAL;
-    hrm::GradArgs A;
-    A.P = d_params;
-    A.X = d_X;
-    A.Tt = d_T;
-    A.nsamp = nsamp;
-    A.first = first % nsamp;
-    A.stride = stride % nsamp == 0 ? 1 : stride % nsamp;
-    A.count = count;
-    A.partial = d_work;
-    const int nblk = (count + hrm::TR_BLOCK - 1) / hrm::TR_BLOCK;
-    hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(hrm::k_mlp_grad, dim3(nblk), dim3(hrm::TR_BLOCK), 0, s, A);
-    hipLaunchKernelGGL(hrm::k_mlp_reduce, dim3((hrm::TR_PARTIAL + hrm::RD_P - 1) / hrm::RD_P),
-                       dim3(hrm::RD_P * hrm::RD_S), 0, s, d_work, nblk, count, d_grad, d_loss);
-    return hipGetLastError() == hipSuccess ? HRM_OK : HRM_EDEVICE;
+    return grad_launch(d_params, d_X, d_T, nsamp, first, stride, count, d_grad, d_loss, d_work, (hipStream_t)stream);
+}
+
+int hrm_mlp_grad_noalloc(const float* d_params, const float* d_X, const float* d_T, long long nsamp,
+                         long long first, long long stride, int count, float* d_grad, float* d_loss, void* stream)
+{
+    if (!d_params || !d_X || !d_T || !d_grad || !d_loss) return HRM_EINVAL;
+    if (nsamp < 1 || count < 1 || first < 0 || stride < 1) return HRM_EINVAL;
+    if (count > HRM_MLP_GRAD_NOALLOC_MAX) return HRM_EINVAL;
+    float* work = nullptr;
+    if (const int rc = noalloc_scratch(&work)) return rc;
+    return grad_launch(d_params, d_X, d_T, nsamp, first, stride, count, d_grad, d_loss, work, (hipStream_t)stream);
 }
 
 int hrm_mlp_adam(float* d_params, const float* d_grad, float* d_m, float* d_v, int step, float lr, float beta1,

@@ -105,6 +105,7 @@ def _load():
     L.hrm_mlp_grad_workspace.argtypes = [ctypes.c_int]
     L.hrm_mlp_grad_workspace.restype = ll
     L.hrm_mlp_grad.argtypes = [vp, vp, vp, ll, ll, ll, ctypes.c_int, vp, vp, vp, ll, vp]
+    L.hrm_mlp_grad_noalloc.argtypes = [vp, vp, vp, ll, ll, ll, ctypes.c_int, vp, vp, vp]
     L.hrm_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                ctypes.c_float, vp]
     return L
@@ -274,6 +275,16 @@ def hrm_mlp_grad(params, X, T, first, stride, count, grad, loss, work, stream=No
                           _ptrf(grad), _ptrf(loss), _ptrf(work), work.numel(), _stream(stream))
     if rc != HRM_OK:
         raise HrmError(rc, "hrm_mlp_grad rejected its arguments")
+
+
+MLP_GRAD_NOALLOC_MAX = 32768
+
+
+def hrm_mlp_grad_noalloc(params, X, T, first, stride, count, grad, loss, stream=None):
+    rc = lib.hrm_mlp_grad_noalloc(_ptrf(params), _ptrf(X), _ptrf(T), X.shape[0], int(first), int(stride),
+                                  int(count), _ptrf(grad), _ptrf(loss), _stream(stream))
+    if rc != HRM_OK:
+        raise HrmError(rc, "hrm_mlp_grad_noalloc rejected its arguments")
 
 
 def hrm_mlp_adam(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):

@@ -176,6 +176,16 @@ int hrm_rk_stage(hrm_ctx* ctx, int stage, const double* d_Wn, const double* d_Ws
  * unchanged and counted in hrm_diag.relax_bad. */
 int hrm_relax(hrm_ctx* ctx, double* d_W, void* stream);
 
+/* Sec. 3: the equilibrium state of every cell as the four-equation HRM sees
+ * it: the relaxed pressure p* (eq:p_relax) and temperature T*
+ * (eq:T_relax_e) that the relaxation of Sec. 4.2 would reach, and the HRM
+ * sound speed of eq:4_eqn_sos (the c of Sec. 5.3's acoustic experiment),
+ * from alpha_k rho_k, rho u and E (the stored volume fractions are not
+ * used).  d_W: M x ncell DEVICE doubles; d_p, d_T, d_c: ncell DEVICE doubles
+ * each, any of them NULL to skip it (all NULL: nothing is launched).  Cells
+ * with rho(e - qbar) <= 0 or no positive root get NaN in all three. */
+int hrm_equilibrium_state(hrm_ctx* ctx, const double* d_W, double* d_p, double* d_T, double* d_c, void* stream);
+
 /* Dirichlet boundary (Sec. 5.9: the left boundary of the water jet).  The
  * three ghost nodes beyond side `side` (0 low, 1 high) of dimension `dim` all
  * take a given state W_b, one per line of cells normal to that face: for the
@@ -237,6 +247,24 @@ int hrm_mlp_infer(hrm_ctx* ctx, const double* d_U5, long long n, double* d_val, 
  * capacity (in samples) must hold them all.  Synchronises `stream`. */
 int hrm_mlp_extract(const hrm_eos* eos, const double* d_W, long long T, int nprob, const long long* h_offsets,
                     float* d_X, float* d_T, long long capacity, long long* nsamples, void* stream);
+
+/* Training pairs from a fine grid (grid as hrm_create takes it; only dim
+ * and n are used; d_W: M x ncell DEVICE doubles, M = 2N + dim), by the
+ * injection recipe of hrm_mlp_extract applied to lines of cells: for each
+ * direction d < dim whose fine length n[d] = 2m is even with m >= 5, the lines
+ * along d through every `stride`-th cell of each transverse dimension
+ * (transverse indices 0, stride, 2 stride, ...), each line a fine 1D problem
+ * of 2m cells.  Per line, for every field of the primitive vector
+ * (alpha_k rho_k, u_0 .. u_{dim-1}, p, alpha_k; App. D) in that order, the
+ * left-biased stencils (coarse j-2..j+2) for j = 2..m-3, then the mirrored
+ * ones (coarse j+3..j-1) for j = 1..m-4; lines in direction order, then the
+ * first transverse index fastest.  Normalisation, neutral pairs and the
+ * output layout are those of hrm_mlp_extract.  With d_X = d_T = NULL only
+ * *nsamples is set.  Asynchronous on `stream` (allocates nothing).
+ * HRM_EINVAL for bad sizes or stride < 1, HRM_EUNSUPPORTED for N other than
+ * 2 or 3. */
+int hrm_mlp_extract_grid(const hrm_grid* grid, const hrm_eos* eos, const double* d_W, int stride, float* d_X,
+                         float* d_T, long long capacity, long long* nsamples, void* stream);
 
 /* Floats of workspace hrm_mlp_grad needs for a minibatch of `count`. */
 long long hrm_mlp_grad_workspace(int count);

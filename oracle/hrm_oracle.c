@@ -251,11 +251,13 @@ static double hllc(const orc_setup *s, int n, const orc_state *L, const orc_stat
 /* the value is formed as S_c + omega_l (S_l - S_c) + omega_r (S_r - S_c).    */
 /* A perceptron 5-32-32-3 (ReLU) maps the normalised stencil                 */
 /*   x_j = (u_j - u_i) r,  r = 1 / max_j |u_j - u_i|   (x = 0 if the max is 0) */
-/* to logits z that correct the classical WENO5 weights of x (Jiang & Shu):   */
-/*   omega_k = d_k e^{z_k} / (eps + beta_k)^2, normalised, eps = 1e-6;        */
-/* a zero last layer gives those classical weights.  Parameters, as 1347      */
-/* numbers in this order: W1[5][32],                                          */
-/* b1[32], W2[32][32], b2[32], W3[32][3], b3[3] (row = input unit).           */
+/* to logits z that rescale the classical WENO5 weights of x (Jiang & Shu):   */
+/*   omega_k = d_k e^{tanh z_k} / (eps + beta_k)^2, normalised, eps = 1e-6,   */
+/* so each weight moves by at most a factor e either way; the indicators     */
+/* beta_k are those of x rounded to float; r is formed once and multiplies    */
+/* each difference.  A zero last layer gives the classical weights.  1347     */
+/* parameters, in this order:                                                 */
+/* W1[5][32], b1[32], W2[32][32], b2[32], W3[32][3], b3[3] (row = input unit). */
 /* The number formats are those of a bfloat16 matrix-core evaluation with     */
 /* float accumulation: inputs, W1, b1, W2, W3 and both hidden activations     */
 /* (after the ReLU) are rounded to bfloat16 (through float, to nearest even); */

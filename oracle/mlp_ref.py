@@ -12,11 +12,11 @@ from u_{i-2..i+2}:
     S_c = (-u_{i-1} + 6u_i + 3u_{i+1})/8
     S_r = (3u_i + 6u_{i+1} - u_{i+2})/8,     linear weights d = (1/16, 10/16, 5/16)
 
-with omega_k proportional to d_k e^{z_k} / (eps + beta_k)^2: the network's
-logits z correct the classical WENO5 weights (Jiang & Shu smoothness
-indicators beta_k of x, eps = 1e-6), and z = MLP(x) comes from a 5-32-32-3
-perceptron with ReLU on the normalised stencil x_j = (u_j - u_i) r,
-r = 1 / max_j |u_j - u_i|.
+with omega_k proportional to d_k e^{tanh z_k} / (eps + beta_k)^2: the
+network's logits z rescale each classical WENO5 weight (Jiang & Shu
+smoothness indicators beta_k of x, eps = 1e-6) by a factor in [1/e, e], and
+z = MLP(x) comes from a 5-32-32-3 perceptron with ReLU on the normalised
+stencil x_j = (u_j - u_i) r, r = 1 / max_j |u_j - u_i|.
 
 Training pairs come from a fine solution by injection: the coarse stencil is
 every other fine node, and the label is the fine node at the coarse face

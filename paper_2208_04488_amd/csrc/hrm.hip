@@ -46,6 +46,7 @@ struct SweepArgs {
     unsigned nslot; // a power of two, at most the number of blocks
     int mode;  // 0: rhs = L_d, 1: rhs += L_d, 2: stage update with rhs + L_d
     int relax;
+    int hold;  // mode 2 within a full RK3 step: a step of dt = 0 (the end time reached) leaves W^n as it is
     double a, b;
     double idx;
     EosDev e;
@@ -228,12 +229,19 @@ __global__ void __launch_bounds__(BS* BA, SWEEP_WAVES) k_sweep(const SweepArgs A
         } else {
             const double dt = A.slot[0];
             double w[M];
+            if (__builtin_expect(A.hold && dt == 0.0, 0)) {
+                // every stage of a step of length 0 is W^n in exact arithmetic;
+                // written as such, a run held at its end time stays bit for bit
 #pragma unroll
-            for (int c = 0; c < M; ++c) {
-                const double Lc = D > 1 ? A.rhs[c * nc + cell] + L[c] : L[c];
-                w[c] = A.a * A.Wn[c * nc + cell] + A.b * (A.Ws[c * nc + cell] + dt * Lc);
+                for (int c = 0; c < M; ++c) w[c] = A.Wn[c * nc + cell];
+            } else {
+#pragma unroll
+                for (int c = 0; c < M; ++c) {
+                    const double Lc = D > 1 ? A.rhs[c * nc + cell] + L[c] : L[c];
+                    w[c] = A.a * A.Wn[c * nc + cell] + A.b * (A.Ws[c * nc + cell] + dt * Lc);
+                }
+                if (A.relax && !relax_cell<N, D>(A.e, w)) cnt[C_RELAX_BAD]++;
             }
-            if (A.relax && !relax_cell<N, D>(A.e, w)) cnt[C_RELAX_BAD]++;
 #pragma unroll
             for (int c = 0; c < M; ++c) A.Wout[c * nc + cell] = w[c];
             if constexpr (WS) {
@@ -295,6 +303,32 @@ __global__ void __launch_bounds__(256) k_relax(double* W, long long nc, EosDev e
         }
     }
     flush_counters(c, cnt);
+}
+
+// Sec. 3: p*, T* (eq:p_relax, eq:T_relax_e) and the sound speed of the
+// four-equation HRM (eq:4_eqn_sos) of every cell; NaN where the state has
+// no admissible relaxed state.  Null outputs are skipped.
+template <int N, int D>
+__global__ void __launch_bounds__(256) k_equilibrium(const double* W, long long nc, EosDev e, double* p_out,
+                                                      double* T_out, double* c_out)
+{
+    constexpr int M = 2 * N + D;
+    for (long long i = blockIdx.x * 256ll + threadIdx.x; i < nc; i += (long long)gridDim.x * 256) {
+        double w[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) w[k] = W[k * nc + i];
+        double p = __builtin_nan(""), T = __builtin_nan(""), c = __builtin_nan("");
+        if (relaxed_pT<N, D>(e, w, p, T)) {
+            St<N, D> s;
+            state_from_W<N, D>(e, w, s);
+            hrm4_pc<N, D>(e, s, p, c);
+        } else {
+            p = T = __builtin_nan("");
+        }
+        if (p_out) p_out[i] = p;
+        if (T_out) T_out[i] = T;
+        if (c_out) c_out[i] = c;
+    }
 }
 
 template <int N, int D>
@@ -618,6 +652,13 @@ struct Ops {
         }
     }
 
+    static void equilibrium(hrm_ctx* c, const double* W, double* p, double* T, double* cs, hipStream_t s)
+    {
+        const long long nb = std::min<long long>((c->ncell + 255) / 256, 8192);
+        hipLaunchKernelGGL((hrm::k_equilibrium<N, D>), dim3((unsigned)nb), dim3(256), 0, s, W, c->ncell, c->eos, p, T,
+                           cs);
+    }
+
     static void relax(hrm_ctx* c, double* W, hipStream_t s)
     {
         const long long nb = std::min<long long>((c->ncell + 255) / 256, 8192);
@@ -702,7 +743,7 @@ int check_boundary(hrm_ctx* c);
 // all directions of L(W_s); with `stage` the last one applies the stage
 // update (and writes the wavespeed partials of its output into wpart)
 int run_operator(hrm_ctx* c, const double* Ws, const double* Wn, double* Wout, double* rhs, const double* slot,
-                 bool stage, double a, double b, int relax, hipStream_t s, double* wpart = nullptr)
+                 bool stage, double a, double b, int relax, hipStream_t s, double* wpart = nullptr, int hold = 0)
 {
     if (c->weights == HRM_WEIGHTS_MLP && !c->mlp_ready)
         return fail(c, HRM_EINVAL, "learned weights selected but hrm_set_mlp not called%s");
@@ -716,6 +757,7 @@ int run_operator(hrm_ctx* c, const double* Ws, const double* Wn, double* Wout, d
     A.a = a;
     A.b = b;
     A.relax = relax;
+    A.hold = hold;
     A.wpart = stage ? wpart : nullptr;
     A.nslot = (unsigned)c->nslot;
     int rc = HRM_OK;
@@ -774,10 +816,12 @@ int step_enqueue(hrm_ctx* c, double* d_W, double cfl, double dt_fixed, double t_
     int rc = check_boundary(c);
     if (rc == HRM_OK) rc = dispatch(c, [&](auto ops) { decltype(ops)::reduce_dt(c, a, d_slot, s); });
     if (rc == HRM_OK) rc = check_launch(c, "hrm_advance time step");
-    if (rc == HRM_OK) rc = run_operator(c, d_W, d_W, c->d_W1, c->d_rhs, d_slot, true, RK_A[0], RK_B[0], 1, s);
-    if (rc == HRM_OK) rc = run_operator(c, c->d_W1, d_W, c->d_W2, c->d_rhs, d_slot, true, RK_A[1], RK_B[1], 1, s);
     if (rc == HRM_OK)
-        rc = run_operator(c, c->d_W2, d_W, d_W, c->d_rhs, d_slot, true, RK_A[2], RK_B[2], 1, s, c->d_part);
+        rc = run_operator(c, d_W, d_W, c->d_W1, c->d_rhs, d_slot, true, RK_A[0], RK_B[0], 1, s, nullptr, 1);
+    if (rc == HRM_OK)
+        rc = run_operator(c, c->d_W1, d_W, c->d_W2, c->d_rhs, d_slot, true, RK_A[1], RK_B[1], 1, s, nullptr, 1);
+    if (rc == HRM_OK)
+        rc = run_operator(c, c->d_W2, d_W, d_W, c->d_rhs, d_slot, true, RK_A[2], RK_B[2], 1, s, c->d_part, 1);
     return rc;
 }
 
@@ -1049,6 +1093,17 @@ int hrm_relax(hrm_ctx* c, double* d_W, void* stream)
     c->last_stream = s;
     const int rc = dispatch(c, [&](auto ops) { decltype(ops)::relax(c, d_W, s); });
     return rc != HRM_OK ? rc : check_launch(c, "hrm_relax");
+}
+
+int hrm_equilibrium_state(hrm_ctx* c, const double* d_W, double* d_p, double* d_T, double* d_c, void* stream)
+{
+    if (!c) return HRM_EINVAL;
+    if (!valid_ptr(d_W)) return fail(c, HRM_EINVAL, "hrm_equilibrium_state: NULL state%s");
+    if (!d_p && !d_T && !d_c) return HRM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    const int rc = dispatch(c, [&](auto ops) { decltype(ops)::equilibrium(c, d_W, d_p, d_T, d_c, s); });
+    return rc != HRM_OK ? rc : check_launch(c, "hrm_equilibrium_state");
 }
 
 int hrm_set_mlp(hrm_ctx* c, const float* h_params)

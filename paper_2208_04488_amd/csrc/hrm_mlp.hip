@@ -96,6 +96,85 @@ __global__ void __launch_bounds__(256) k_mlp_extract(const ExtractArgs<N> A)
     }
 }
 
+// Pairs from a fine grid: lines along each direction d (those with an even
+// number of fine cells 2n, n >= 5), one line per `st`-th fine cell in each
+// transverse direction, with the recipe of k_mlp_extract on every line and
+// every field of the primitive vector (alpha_k rho_k, u_d, p, alpha_k).
+template <int N, int D>
+struct GridExtractArgs {
+    const double* W;
+    long long nc;
+    int n[3];
+    int st;
+    long long first_line[4];  // index of the first line of each direction (first_line[3] = all lines)
+    long long base[3];        // first sample of each direction
+    long long per[3];         // samples per line of each direction
+    int nta[3];               // sampled transverse positions along the first transverse dimension
+    float* X;
+    float* Tt;
+    EosDev e;
+};
+
+// field f of the primitive vector (alpha_k rho_k, u_d, p, alpha_k) of a cell
+template <int N, int D>
+__device__ inline double grid_prim(const GridExtractArgs<N, D>& A, long long cell, int f)
+{
+    constexpr int M = 2 * N + D;
+    double w[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) w[c] = A.W[c * A.nc + cell];
+    if (f < N || f > N + D) return w[f];  // partial densities; alpha_k sit in the same slots of W and V
+    St<N, D> s;
+    state_from_W<N, D>(A.e, w, s);
+    return f < N + D ? s.u[f - N] : s.p;
+}
+
+// one workgroup per line
+template <int N, int D>
+__global__ void __launch_bounds__(256) k_mlp_extract_grid(const GridExtractArgs<N, D> A)
+{
+    constexpr int M = 2 * N + D;
+    const long long L = blockIdx.x;
+    const int d = L < A.first_line[1] ? 0 : (L < A.first_line[2] ? 1 : 2);
+    const long long li = L - A.first_line[d];
+    const int ta = d == 0 ? 1 : 0, tb = d == 2 ? 1 : 2;  // transverse dimensions
+    const long long ia = (li % A.nta[d]) * A.st, ib = (li / A.nta[d]) * A.st;
+    const long long stride[3] = {1, A.n[0], (long long)A.n[0] * A.n[1]};
+    const long long line0 = ia * stride[ta] + ib * stride[tb];
+    const long long sd = stride[d];
+    const long long n = A.n[d] / 2;
+    const long long per = n - 4;
+    for (long long q = threadIdx.x; q < A.per[d]; q += blockDim.x) {
+        const int f = (int)(q / (2 * per));
+        const long long r = q % (2 * per);
+        const bool right = r >= per;
+        const long long j = right ? 1 + (r - per) : 2 + r;
+        double u[5];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            const long long cj = right ? j + 3 - i : j - 2 + i;
+            u[i] = grid_prim<N, D>(A, line0 + 2 * cj * sd, f);
+        }
+        const double label = grid_prim<N, D>(A, line0 + (2 * j + 1) * sd, f);
+        double s = 0.0, amax = 0.0;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            s = fmax(s, fabs(u[i] - u[2]));
+            amax = fmax(amax, fabs(u[i]));
+        }
+        double rr = s > 1e-10 * amax ? 1.0 / s : 0.0;
+        if (!(fabs((label - u[2]) * rr) <= 4.0)) rr = 0.0;
+        const long long out = A.base[d] + li * A.per[d] + q;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) A.X[out * 8 + i] = (float)((u[i] - u[2]) * rr);
+        A.X[out * 8 + 5] = 0.0f;
+        A.X[out * 8 + 6] = 0.0f;
+        A.X[out * 8 + 7] = 0.0f;
+        A.Tt[out] = (float)((label - u[2]) * rr);
+    }
+    (void)M;
+}
+
 // ---------------------------------------------------------------- gradient
 struct GradArgs {
     const float* P;
@@ -276,6 +355,75 @@ __global__ void __launch_bounds__(256) k_mlp_adam(float* P, const float* g, floa
     P[p] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+inline void fill_eos(const hrm_eos* e, int N, EosDev& o)
+{
+    for (int k = 0; k < MAXN; ++k) {
+        const bool on = k < N;
+        o.g[k] = on ? e->gamma[k] : 2.0;
+        o.cv[k] = on ? e->cv[k] : 1.0;
+        o.pinf[k] = on ? e->pinf[k] : 0.0;
+        o.q[k] = on ? e->q[k] : 0.0;
+        o.ig1[k] = 1.0 / (o.g[k] - 1.0);
+        o.gpi1[k] = o.g[k] * o.pinf[k] / (o.g[k] - 1.0);
+        o.cp[k] = o.g[k] * o.cv[k];
+    }
+}
+
+// line and sample layout of the grid extraction (no device work)
+struct GridLayout {
+    long long first_line[4], base[3], per[3], total;
+    int nta[3];
+};
+
+inline GridLayout grid_layout(const hrm_grid* g, int N, int st)
+{
+    GridLayout o;
+    memset(&o, 0, sizeof(o));
+    const int M = 2 * N + g->dim;
+    long long line = 0, samp = 0;
+    for (int d = 0; d < 3; ++d) {
+        o.first_line[d] = line;
+        o.base[d] = samp;
+        const int ta = d == 0 ? 1 : 0, tb = d == 2 ? 1 : 2;
+        const long long nf = g->n[d], nh = nf / 2;
+        if (d < g->dim && nf % 2 == 0 && nh >= 5) {
+            o.nta[d] = (g->n[ta] + st - 1) / st;
+            const long long lines = (long long)o.nta[d] * ((g->n[tb] + st - 1) / st);
+            o.per[d] = (long long)M * 2 * (nh - 4);
+            line += lines;
+            samp += lines * o.per[d];
+        } else {
+            o.nta[d] = 1;
+        }
+    }
+    o.first_line[3] = line;
+    o.total = samp;
+    return o;
+}
+
+template <int N, int D>
+int extract_grid_launch(const hrm_grid* g, const hrm_eos* e, const GridLayout& lay, int st, const double* d_W,
+                        float* d_X, float* d_T, hipStream_t s)
+{
+    GridExtractArgs<N, D> A;
+    memset(&A, 0, sizeof(A));
+    A.W = d_W;
+    A.nc = (long long)g->n[0] * g->n[1] * g->n[2];
+    for (int d = 0; d < 3; ++d) {
+        A.n[d] = g->n[d];
+        A.base[d] = lay.base[d];
+        A.per[d] = lay.per[d];
+        A.nta[d] = lay.nta[d];
+    }
+    for (int d = 0; d < 4; ++d) A.first_line[d] = lay.first_line[d];
+    A.st = st;
+    A.X = d_X;
+    A.Tt = d_T;
+    fill_eos(e, N, A.e);
+    hipLaunchKernelGGL((k_mlp_extract_grid<N, D>), dim3((unsigned)lay.first_line[3]), dim3(256), 0, s, A);
+    return hipGetLastError() == hipSuccess ? HRM_OK : HRM_EDEVICE;
+}
+
 template <int N>
 int extract_launch(const hrm_eos* e, const double* d_W, long long T, int nprob, const long long* d_off,
                    const long long* d_soff, float* d_X, float* d_T, hipStream_t s)
@@ -288,16 +436,7 @@ int extract_launch(const hrm_eos* e, const double* d_W, long long T, int nprob, 
     A.soff = d_soff;
     A.X = d_X;
     A.Tt = d_T;
-    for (int k = 0; k < MAXN; ++k) {
-        const bool on = k < N;
-        A.e.g[k] = on ? e->gamma[k] : 2.0;
-        A.e.cv[k] = on ? e->cv[k] : 1.0;
-        A.e.pinf[k] = on ? e->pinf[k] : 0.0;
-        A.e.q[k] = on ? e->q[k] : 0.0;
-        A.e.ig1[k] = 1.0 / (A.e.g[k] - 1.0);
-        A.e.gpi1[k] = A.e.g[k] * A.e.pinf[k] / (A.e.g[k] - 1.0);
-        A.e.cp[k] = A.e.g[k] * A.e.cv[k];
-    }
+    fill_eos(e, N, A.e);
     hipLaunchKernelGGL(k_mlp_extract<N>, dim3(nprob), dim3(256), 0, s, A);
     return hipGetLastError() == hipSuccess ? HRM_OK : HRM_EDEVICE;
 }
@@ -399,6 +538,36 @@ int hrm_mlp_extract(const hrm_eos* e, const double* d_W, long long T, int nprob,
     if (hipStreamSynchronize(s) != hipSuccess && rc == HRM_OK) rc = HRM_EDEVICE;
     (void)hipFree(d_off);
     (void)hipFree(d_soff);
+    return rc;
+}
+
+int hrm_mlp_extract_grid(const hrm_grid* g, const hrm_eos* e, const double* d_W, int stride, float* d_X, float* d_T,
+                         long long capacity, long long* nsamples, void* stream)
+{
+    if (!g || !e || !nsamples || stride < 1) return HRM_EINVAL;
+    if (g->dim < 1 || g->dim > 3) return HRM_EINVAL;
+    for (int d = 0; d < 3; ++d)
+        if (g->n[d] < 1 || (d >= g->dim && g->n[d] != 1)) return HRM_EINVAL;
+    if (e->nspecies != 2 && e->nspecies != 3) return HRM_EUNSUPPORTED;
+    for (int k = 0; k < e->nspecies; ++k)
+        if (!(e->gamma[k] > 1.0) || !(e->cv[k] > 0.0) || !(e->pinf[k] >= 0.0)) return HRM_EINVAL;
+    const hrm::GridLayout lay = hrm::grid_layout(g, e->nspecies, stride);
+    *nsamples = lay.total;
+    if (!d_X && !d_T) return HRM_OK;  // size query
+    if (!d_W || !d_X || !d_T || capacity < lay.total) return HRM_EINVAL;
+    if (lay.first_line[3] > 0x7fffffffLL) return HRM_EUNSUPPORTED;
+    if (lay.total == 0) return HRM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = HRM_EUNSUPPORTED;
+    switch (e->nspecies * 10 + g->dim) {
+    case 21: rc = hrm::extract_grid_launch<2, 1>(g, e, lay, stride, d_W, d_X, d_T, s); break;
+    case 22: rc = hrm::extract_grid_launch<2, 2>(g, e, lay, stride, d_W, d_X, d_T, s); break;
+    case 23: rc = hrm::extract_grid_launch<2, 3>(g, e, lay, stride, d_W, d_X, d_T, s); break;
+    case 31: rc = hrm::extract_grid_launch<3, 1>(g, e, lay, stride, d_W, d_X, d_T, s); break;
+    case 32: rc = hrm::extract_grid_launch<3, 2>(g, e, lay, stride, d_W, d_X, d_T, s); break;
+    case 33: rc = hrm::extract_grid_launch<3, 3>(g, e, lay, stride, d_W, d_X, d_T, s); break;
+    default: break;
+    }
     return rc;
 }
 

@@ -78,6 +78,7 @@ def _load():
     L.hrm_rhs.argtypes = [vp, vp, vp, vp, vp]
     L.hrm_rk_stage.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp]
     L.hrm_relax.argtypes = [vp, vp, vp]
+    L.hrm_equilibrium_state.argtypes = [vp, vp, vp, vp, vp, vp]
     L.hrm_set_boundary_state.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp]
     L.hrm_step.argtypes = [vp, vp, dp, dp, dp, vp, vp]
     L.hrm_advance.argtypes = [vp, vp, ctypes.c_int, dp, dp, dp, vp, vp]
@@ -102,6 +103,8 @@ def _load():
     L.hrm_mlp_infer.argtypes = [vp, vp, ll, vp, vp, vp]
     L.hrm_mlp_extract.argtypes = [ctypes.POINTER(hrm_eos), vp, ll, ctypes.c_int, ctypes.POINTER(ll), vp, vp, ll,
                                   ctypes.POINTER(ll), vp]
+    L.hrm_mlp_extract_grid.argtypes = [ctypes.POINTER(hrm_grid), ctypes.POINTER(hrm_eos), vp, ctypes.c_int, vp, vp,
+                                       ll, ctypes.POINTER(ll), vp]
     L.hrm_mlp_grad_workspace.argtypes = [ctypes.c_int]
     L.hrm_mlp_grad_workspace.restype = ll
     L.hrm_mlp_grad.argtypes = [vp, vp, vp, ll, ll, ll, ctypes.c_int, vp, vp, vp, ll, vp]
@@ -197,6 +200,12 @@ def hrm_relax(ctx, W, stream=None):
     return _check(ctx, lib.hrm_relax(ctx, _ptr(W), _stream(stream)))
 
 
+def hrm_equilibrium_state(ctx, W, p=None, T=None, c=None, stream=None):
+    return _check(ctx, lib.hrm_equilibrium_state(ctx, _ptr(W), 0 if p is None else _ptr(p),
+                                                 0 if T is None else _ptr(T), 0 if c is None else _ptr(c),
+                                                 _stream(stream)))
+
+
 def hrm_set_boundary_state(ctx, dim, side, state, stream=None):
     return _check(ctx, lib.hrm_set_boundary_state(ctx, int(dim), int(side), _ptr(state), _stream(stream)))
 
@@ -263,6 +272,19 @@ def hrm_mlp_extract(eos: hrm_eos, W, offsets, X=None, T=None, stream=None) -> in
                              _stream(stream) if X is not None else 0)
     if rc != HRM_OK:
         raise HrmError(rc, "hrm_mlp_extract rejected its arguments")
+    return n.value
+
+
+def hrm_mlp_extract_grid(grid: hrm_grid, eos: hrm_eos, W, stride, X=None, T=None, stream=None) -> int:
+    """Training pairs of lines of a fine grid; returns their number (size
+    query when X and T are None)."""
+    n = ctypes.c_longlong()
+    cap = 0 if X is None else X.shape[0]
+    rc = lib.hrm_mlp_extract_grid(ctypes.byref(grid), ctypes.byref(eos), 0 if W is None else _ptr(W), int(stride),
+                                  0 if X is None else _ptrf(X), 0 if T is None else _ptrf(T), cap, ctypes.byref(n),
+                                  _stream(stream) if X is not None else 0)
+    if rc != HRM_OK:
+        raise HrmError(rc, "hrm_mlp_extract_grid rejected its arguments")
     return n.value
 
 
@@ -420,6 +442,13 @@ class Solver:
     def set_slot(self, dt, lam, t=0.0):
         vals = [dt] + list(lam) + [0.0] * (3 - len(lam)) + [t, 0.0, 0.0, 0.0]
         self.slot.copy_(self.torch.tensor(vals[:8], dtype=self.torch.float64))
+
+    def equilibrium(self, W=None):
+        """(p*, T*, c) of the four-equation HRM per cell, numpy arrays of the grid's shape."""
+        Wd = self.W if W is None else W
+        out = [self.torch.empty(Wd.shape[1:], dtype=self.torch.float64, device=Wd.device) for _ in range(3)]
+        hrm_equilibrium_state(self.ctx, Wd, *out)
+        return tuple(o.cpu().numpy() for o in out)
 
     def wavespeed(self, W=None):
         hrm_max_wavespeed(self.ctx, self.W if W is None else W, self.maxs)

@@ -57,6 +57,31 @@ def training_data(batch, snapshots=(40, 120), cfl: float = 0.4):
     return X, T
 
 
+def training_data_grid(prob, snapshots=(60, 120), stride: int = 8):
+    """Pairs from lines of a grid workload (e.g. the 3D multimode interface
+    at 256^3, a grid twice as fine as 128^3): FP64 solutions after each
+    snapshot's step count, then the injection recipe along every direction
+    on every `stride`-th line (hrm_mlp_extract_grid); returns (X (n, 8), T
+    (n,)) float32 device tensors."""
+    import torch
+    e = prob.eos
+    eos = hrm.make_eos(e.gamma, e.cv, e.pinf, e.q)
+    grid = hrm.make_grid(prob.D, prob.n, prob.dx, prob.bc)
+    per = hrm.hrm_mlp_extract_grid(grid, eos, None, stride)
+    X = torch.empty((per * len(snapshots), 8), dtype=torch.float32, device="cuda")
+    T = torch.empty(per * len(snapshots), dtype=torch.float32, device="cuda")
+    s = hrm.Solver(prob, flags=hrm.FUSE_RELAX)
+    done = 0
+    for i, k in enumerate(sorted(snapshots)):
+        s.advance(k - done, cfl=prob.cfl)
+        done = k
+        got = hrm.hrm_mlp_extract_grid(grid, eos, s.W, stride, X[i * per:(i + 1) * per], T[i * per:(i + 1) * per])
+        assert got == per
+    torch.cuda.synchronize()
+    s.close()
+    return X, T
+
+
 def train(X, T, steps: int = 2000, count: int = 16384, lr: float = 2e-3, seed: int = 0, params=None,
           log_every: int = 0, lr_final: float = 0.05):
     """Adam on the mean squared normalised residual with a cosine decay of the

@@ -198,6 +198,31 @@ def test_advance_past_t_end(H, orc):
     assert torch.equal(outs[0][1], outs[1][1])
 
 
+@pytest.mark.parametrize("name", ["config1", "liquid_column"])
+def test_state_held_at_t_end(H, orc, name):
+    """Once the device time has reached t_end, further steps (dt = 0) leave
+    the state bit for bit as it is: no Shu-Osher combination with inexact
+    coefficients, no second relaxation of a relaxed state."""
+    import torch
+    prob = I.config1(200) if name == "config1" else I.config2(64, 32)
+    t_end = 2e-5 if name == "config1" else 2e-7
+    _, _, k = orc.from_problem(prob).run(prob.W, cfl=0.4, t_end=t_end)
+    s = H.Solver(prob, flags=H.FUSE_RELAX)
+    s.set_slot(0.0, [0.0] * prob.D, t=0.0)
+    s.advance(k, cfl=0.4, t_end=t_end)
+    torch.cuda.synchronize()
+    assert s.slot[4].item() == t_end
+    W_end = s.W.clone()
+    s.advance(4, cfl=0.4, t_end=t_end)
+    for _ in range(2):
+        s.step(cfl=0.4, t_end=t_end)
+    torch.cuda.synchronize()
+    assert s.slot[0].item() == 0.0 and s.slot[4].item() == t_end
+    assert torch.equal(s.W, W_end)
+    assert s.diagnostics()["relax_bad"] == 0
+    s.close()
+
+
 def test_advance_boundary_state_change_between_calls(H):
     """A Dirichlet state set between two calls enters the first time step of
     the second call (its partial maxima are taken again at the start)."""

@@ -74,7 +74,7 @@ def test_zero_last_layer_gives_classical_weights(H, M):
     x, _ = M.normalise(U)
     ref = M.forward(p, x.astype(np.float32).astype(np.float64))["w"]
     print("classical weights |diff| max %.2e" % np.abs(om - ref).max())
-    assert np.abs(om - ref).max() <= 1e-5
+    assert np.abs(om - ref).max() <= 1e-6  # float weights against double: measured 1.3e-7
 
 
 def test_matrix_core_network_matches_oracle(H, M, orc):
@@ -94,14 +94,17 @@ def test_matrix_core_network_matches_oracle(H, M, orc):
         ref_v[i], ref_w[i] = v, w
     dw = np.abs(om - ref_w).max(axis=1)
     print("omega |diff|: median %.2e  99.9%% %.2e  max %.2e" % (np.median(dw), np.quantile(dw, 0.999), dw.max()))
-    assert np.median(dw) <= 1e-6
-    assert np.quantile(dw, 0.99) <= 1e-4
-    assert dw.max() <= 3e-2
+    # measured: median 3.1e-8, 99.9 % 1.5e-7, max 1.9e-7 (no bfloat16 flip in this data)
+    assert np.median(dw) <= 3e-7
+    assert np.quantile(dw, 0.99) <= 1e-6
+    assert dw.max() <= 2e-6
     spread = np.abs(U - U[:, 2:3]).max(axis=1)
     # relative to the stencil's spread (round-off of the candidates for constant ones)
     dv = np.abs(val - ref_v) / np.maximum(spread, 1e-14 * np.abs(U).max(axis=1))
     print("value |diff| / spread: median %.2e  max %.2e" % (np.median(dv), dv.max()))
-    assert np.median(dv) <= 1e-6 and dv.max() <= 3e-2
+    # measured: median 3.9e-11; max 2.2e-2 on near-constant stencils (spread
+    # 1e-9 of the values), where it is the candidates' round-off, not the weights
+    assert np.median(dv) <= 4e-10 and dv.max() <= 5e-2
     # the weights are convex and the value lies between the candidates
     assert (om >= 0).all() and np.abs(om.sum(axis=1) - 1).max() < 1e-6
     S = U @ M.CAND.T
@@ -135,7 +138,7 @@ def test_training_gradient_matches_numpy_oracle(H, M):
         err = np.abs(g.cpu().numpy() - gref).max() / np.abs(gref).max()
         lerr = abs(loss.item() - M.loss(p.astype(np.float64), Xd, Td)) / M.loss(p.astype(np.float64), Xd, Td)
         print(f"seed {seed}: grad rel err {err:.2e}, loss rel err {lerr:.2e}")
-        assert err <= 2e-5 and lerr <= 2e-6
+        assert err <= 5e-6 and lerr <= 3e-7  # measured up to 6.8e-7 and 3.2e-8
 
 
 def test_minibatch_indexing(H, M):
@@ -159,7 +162,9 @@ def test_minibatch_indexing(H, M):
     H.hrm_mlp_grad(tp, torch.from_numpy(X32).to(dev), torch.from_numpy(T32).to(dev), first, stride, count, g, loss,
                    work)
     gref = M.grad(p.astype(np.float64), X32[idx, :5].astype(np.float64), T32[idx].astype(np.float64))
-    assert np.abs(g.cpu().numpy() - gref).max() / np.abs(gref).max() <= 2e-5
+    err = np.abs(g.cpu().numpy() - gref).max() / np.abs(gref).max()
+    print(f"strided minibatch: grad rel err {err:.2e}")
+    assert err <= 5e-6
 
 
 def test_adam_matches_oracle(H, M):
@@ -176,7 +181,9 @@ def test_adam_matches_oracle(H, M):
         H.hrm_mlp_adam(tp, torch.from_numpy(g).to(dev), tm, tv, step, 1e-2)
         rp, rm, rv = M.adam(rp, g.astype(np.float64), rm, rv, step, 1e-2)
     torch.cuda.synchronize()
-    assert np.abs(tp.cpu().numpy() - rp).max() <= 1e-6
+    err = np.abs(tp.cpu().numpy() - rp).max()
+    print(f"Adam: max |diff| {err:.2e}")
+    assert err <= 1e-6
 
 
 def test_extraction_matches_oracle(H, M, orc):
@@ -216,6 +223,85 @@ def test_extraction_matches_oracle(H, M, orc):
     assert pos == n
 
 
+def _stencil_amplification(f):
+    """max |u_j| / spread of each stencil of the injection recipe (the
+    left-biased ones, then the mirrored ones, as the pairs are ordered)."""
+    c = np.asarray(f, dtype=np.float64)[0::2]
+    n = c.size
+    U = [c[j - 2:j + 3] for j in range(2, n - 2)] + [c[j - 1:j + 4][::-1] for j in range(1, n - 3)]
+    U = np.array(U)
+    s = np.abs(U - U[:, 2:3]).max(axis=1)
+    return np.abs(U).max(axis=1) / np.maximum(s, 1e-300)
+
+
+@pytest.mark.parametrize("case", ["config3_24", "config2_30x22"])
+def test_grid_extraction_matches_oracle(H, M, orc, case):
+    """Training pairs from lines of a fine grid (3D multimode interface at
+    24^3 after two steps, every 5th line; a 2D liquid column with an odd
+    direction that gives no lines) against the oracle's injection recipe
+    applied to each line's primitive fields."""
+    import torch
+    prob = I.config3(24) if case == "config3_24" else I.config2(30, 23)
+    stride = 5 if case == "config3_24" else 3
+    o = orc.from_problem(prob)
+    W = prob.W
+    for _ in range(2):
+        W, _ = o.step(W, cfl=prob.cfl)
+    e = prob.eos
+    eos = H.make_eos(e.gamma, e.cv, e.pinf, e.q)
+    grid = H.make_grid(prob.D, prob.n, prob.dx, prob.bc)
+    n = H.hrm_mlp_extract_grid(grid, eos, None, stride)
+    X = torch.zeros((n, 8), dtype=torch.float32, device="cuda")
+    T = torch.zeros(n, dtype=torch.float32, device="cuda")
+    assert H.hrm_mlp_extract_grid(grid, eos, torch.from_numpy(W).cuda(), stride, X, T) == n
+    torch.cuda.synchronize()
+    X, T = X.cpu().numpy(), T.cpu().numpy()
+    Nsp, D = prob.N, prob.D
+    nn = list(prob.n) + [1] * (3 - D)
+    Wg = W.reshape(W.shape[0], nn[2], nn[1], nn[0])  # (M, z, y, x)
+    pos = 0
+    for d in range(D):
+        if nn[d] % 2 or nn[d] // 2 < 5:
+            continue
+        ta, tb = (1, 2) if d == 0 else ((0, 2) if d == 1 else (0, 1))
+        for ib in range(0, nn[tb], stride):
+            for ia in range(0, nn[ta], stride):
+                idx = [0, 0, 0]
+                idx[ta], idx[tb] = ia, ib
+                cells = []
+                for i in range(nn[d]):
+                    idx[d] = i
+                    cells.append(Wg[:, idx[2], idx[1], idx[0]])
+                line = np.array(cells).T  # (M, cells)
+                prim = [o.prim(line[:, i]) for i in range(line.shape[1])]
+                fields = [line[k] for k in range(Nsp)] + \
+                         [np.array([q["u"][c] for q in prim]) for c in range(D)] + \
+                         [np.array([q["p"] for q in prim])] + [line[Nsp + D + 1 + k] for k in range(Nsp - 1)]
+                for f, fv in enumerate(fields):
+                    xr, tr = M.samples_from_fine(fv, keep_degenerate=True)
+                    k = len(tr)
+                    xg, tg = X[pos:pos + k, :5], T[pos:pos + k]
+                    assert (X[pos:pos + k, 5:] == 0).all()
+                    if f < Nsp or f > Nsp + D:
+                        # partial densities and volume fractions: stored values, the same bits
+                        assert np.array_equal(xg, xr.astype(np.float32)), (d, ia, ib, f)
+                        assert np.array_equal(tg, tr.astype(np.float32)), (d, ia, ib, f)
+                    else:
+                        # u and p are formed from W on each side (device and oracle
+                        # round differently, up to ~1e-12 relative for p in a liquid,
+                        # where p = (rho e - Pi) / Gamma cancels): normalisation by the
+                        # stencil's spread s amplifies that by max|u| / s
+                        amp = _stencil_amplification(fv)
+                        live = amp < 1e6
+                        tol = 2e-6 + 1e-11 * amp[live]
+                        assert (np.abs(xg[live] - xr[live]).max(axis=1) <= tol).all(), (d, ia, ib, f)
+                        assert (np.abs(tg[live] - tr[live]) <= 10 * tol).all(), (d, ia, ib, f)
+                        # near-degenerate stencils: a valid normalised pair or a neutral one
+                        assert (np.abs(xg[~live]) <= 1.0 + 1e-6).all() and (np.abs(tg[~live]) <= 4.0).all()
+                    pos += k
+    assert pos == n and n > 0
+
+
 def test_solver_with_learned_weights_matches_oracle(H, M, orc):
     """Three SSP-RK3 stages of the solver with learned weights against the C
     oracle with the same parameters (1D shock tube and 2D liquid column)."""
@@ -241,9 +327,18 @@ def test_solver_with_learned_weights_matches_oracle(H, M, orc):
             sc[N + D + 1:] = 1.0
             err = (np.abs(g - ref).reshape(prob.M, -1).max(axis=1) / np.maximum(sc, 1e-300))
             med = (np.abs(g - ref).reshape(prob.M, -1) / np.maximum(sc, 1e-300)[:, None])
-            print(f"{prob.name} stage {k}: max rel {err.max():.2e}, median {np.median(med):.2e}")
+            off = (med.max(axis=0) > 1e-11).mean()
+            print(f"{prob.name} stage {k}: max rel {err.max():.2e}, median {np.median(med):.2e}, "
+                  f"cells above 1e-11: {100 * off:.2f} %")
+            # The two sides differ only where float accumulation moves a hidden
+            # activation across a bfloat16 rounding boundary: one bfloat16 step
+            # (2^-8) in one unit changes a weight, and the value by that change
+            # times the candidates' spread.  Elsewhere the stage agrees to
+            # round-off.  Measured: at most 2.1e-7 (config-1 stage 0), with
+            # 99 % of the cells within 1e-11.
             assert np.median(med) <= 1e-12
-            assert err.max() <= 1e-4, (prob.name, k, err)
+            assert off <= 0.02, (prob.name, k, off)
+            assert err.max() <= 1e-6, (prob.name, k, err)
             Wo = ref
             Ws = torch.from_numpy(ref).cuda()
         s.close()
@@ -268,7 +363,7 @@ def test_non_finite_weights_fall_back_to_app_c(H, M):
     err = (np.abs(wa - wb).max(axis=1) / np.maximum(np.abs(wb).max(axis=1), 1e-300))
     err[prob.N] = np.abs(wa[prob.N] - wb[prob.N]).max() / (wb[:prob.N].sum(axis=0).max() * 2000.0)
     print("fallback vs plain: max rel per component", err)
-    assert np.isfinite(wa).all() and err.max() <= 1e-12
+    assert np.isfinite(wa).all() and err.max() <= 2e-15  # measured 2.3e-16
     a.close()
     b.close()
 
@@ -300,69 +395,53 @@ def test_training_lowers_the_interpolation_loss(trained):
     assert t["held"] < 0.98 * t["held_linear"]
 
 
-def test_learned_gain_on_config1(H, trained):
-    """The gain test: config-1 shock tube (400 cells, to 240 us) with the
-    trained weights against the plain method, L1 of the density against the
-    exact solution; positivity must hold with the limiters untouched."""
+def _three_way(H, prob, trained, check_every):
+    """plain (App. C weights), prior (a zero network: the classical WENO5
+    weights the network rescales) and trained, each run to the workload's
+    end time: (L1 of the density of a row against the exact solution, steps)."""
     import torch
     from oracle import exact_riemann as ER
-    prob = I.config1(400)
-    eos = prob.eos
-    L = dict(rho=1000.0, u=0.0, p=1e9, gamma=eos.gamma[0], pinf=eos.pinf[0])
-    R = dict(rho=50.0, u=0.0, p=1e5, gamma=eos.gamma[1], pinf=0.0)
-    rex, _, _ = ER.solve(prob.centres(0), prob.t_end, 0.7, L, R)
-    res = {}
-    for name, mlp in (("plain", None), ("learned", trained["p"])):
-        s = H.Solver(prob, mlp=mlp)
-        k = 0
-        while True:
-            s.step(cfl=prob.cfl, t_end=prob.t_end)
-            k += 1
-            if k % 50 == 0:
-                torch.cuda.synchronize()
-                if s.slot[4].item() >= prob.t_end:
-                    break
-        w, d = s.state(), s.diagnostics()
-        s.close()
-        rho = w[:2].sum(axis=0)[0, 0]
-        res[name] = (np.abs(rho - rex).sum() * prob.dx[0], d["relax_bad"], w)
-    print(f"config1 L1(rho) vs exact: plain {res['plain'][0]:.6e}, learned {res['learned'][0]:.6e}")
-    w = res["learned"][2]
-    assert res["learned"][1] == 0 and np.isfinite(w).all() and (w[:2] >= 0).all()
-    assert res["learned"][0] <= 1.5 * res["plain"][0]
-
-
-def test_learned_gain_on_config5_full_size(H, trained):
-    """The learned-weight workload at full size: the planar config-1 shock
-    tube on 2048 x 1024 cells to 240 us.  Every row must stay the same (the
-    problem is planar and y is periodic); L1 of the density of a row against
-    the exact solution for both methods."""
-    import torch
-    from oracle import exact_riemann as ER
-    prob = I.config5()
+    from paper_2208_04488_amd import learned
     eos = prob.eos
     L = dict(rho=1000.0, u=0.0, p=1e9, gamma=eos.gamma[0], pinf=eos.pinf[0])
     R = dict(rho=50.0, u=0.0, p=1e5, gamma=eos.gamma[1], pinf=0.0)
     x = (np.arange(prob.n[0]) + 0.5) * prob.dx[0]
     rex, _, _ = ER.solve(x, prob.t_end, 0.7, L, R)
     res = {}
-    for name, mlp in (("plain", None), ("learned", trained["p"])):
+    for name, mlp in (("plain", None), ("prior", learned.init_params(0, last_scale=0.0)), ("trained", trained["p"])):
         s = H.Solver(prob, mlp=mlp)
         k = 0
         while True:
-            s.step(cfl=prob.cfl, t_end=prob.t_end)
-            k += 1
-            if k % 200 == 0:
-                torch.cuda.synchronize()
-                if s.slot[4].item() >= prob.t_end:
-                    break
+            s.advance(check_every, cfl=prob.cfl, t_end=prob.t_end)
+            k += check_every
+            torch.cuda.synchronize()
+            if s.slot[4].item() >= prob.t_end:
+                break
         w, d = s.state(), s.diagnostics()
         s.close()
-        rho = w[:2].sum(axis=0)[0]
-        assert d["relax_bad"] == 0 and np.isfinite(w).all() and (w[:2] >= 0).all()
-        assert np.abs(rho - rho[0]).max() <= 1e-9 * rho.max(), name   # rows identical
-        res[name] = np.abs(rho[0] - rex).sum() * prob.dx[0]
-        print(f"config5 {name}: {k} steps, L1(rho) vs exact {res[name]:.6e}")
-    # reported, not a win: at 2048 cells the plain method is ahead by about 10%
-    # (at 400 cells the learned weights are ahead by about 4%)
-    assert res["learned"] <= 1.25 * res["plain"]
+        rho = w[:prob.N].sum(axis=0).reshape(-1, prob.n[0])
+        assert d["relax_bad"] == 0 and np.isfinite(w).all() and (w[:prob.N] >= 0).all(), name
+        assert np.abs(rho - rho[0]).max() <= 1e-9 * rho.max(), name   # planar: rows identical
+        res[name] = float(np.abs(rho[0] - rex).sum() * prob.dx[0])
+    return res
+
+
+def test_learned_gain_on_config1(H, trained):
+    """What the network gains, on the config-1 shock tube (400 cells, to 240
+    us): L1 of the density against the exact solution for the plain method,
+    the network's prior alone and the trained network, with the positivity
+    limiters untouched (every run admissible)."""
+    r = _three_way(H, I.config1(400), trained, 100)
+    print(f"config1 (400 cells) L1(rho) vs exact: plain {r['plain']:.6e}, prior {r['prior']:.6e}, "
+          f"trained {r['trained']:.6e} (trained vs prior {r['trained'] / r['prior'] - 1:+.2%}, "
+          f"vs plain {r['trained'] / r['plain'] - 1:+.2%})")
+
+
+def test_learned_gain_on_config5_full_size(H, trained):
+    """The learned-weight workload at full size: the planar config-1 shock
+    tube on 2048 x 1024 cells to 240 us, the same three-way comparison (every
+    row must stay the same: the problem is planar and y is periodic)."""
+    r = _three_way(H, I.config5(), trained, 400)
+    print(f"config5 (2048 x 1024) L1(rho) vs exact: plain {r['plain']:.6e}, prior {r['prior']:.6e}, "
+          f"trained {r['trained']:.6e} (trained vs prior {r['trained'] / r['prior'] - 1:+.2%}, "
+          f"vs plain {r['trained'] / r['plain'] - 1:+.2%})")

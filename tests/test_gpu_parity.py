@@ -48,6 +48,51 @@ def rel_err(A, B, N, D, cmax):
     return (np.abs(A - B).reshape(M, -1).max(axis=1) / s).max()
 
 
+TRACE = 1e-6        # a species is a trace in a cell where its volume fraction is below this
+# Relative bar of trace cells whose stencil reach holds no bulk of the
+# species.  Every term of such a cell's update scales with the trace, so the
+# face arithmetic agrees to tens of ulps; the relaxation then sets a trace
+# gas's alpha_k = alpha_k rho_k / rho_k(p*, T*), and in a liquid at low
+# pressure p* is kappa = gamma_1 p_inf,1 / p (2e4 for the droplets at 1 bar)
+# times more sensitive than rho e-tilde, so its relative error can reach
+# kappa x tens of ulps, ~1e-10.  Measured: 6.2e-13 at 256^3 (liquid droplets
+# with gas traces at 1 bar), 3e-14 or less on the other workloads.
+TRACE_ISOLATED = 1e-10
+
+
+def trace_errors(A, B, N, D):
+    """Errors of the trace quantities the limiters guard: alpha_k rho_k (all
+    k) and the stored alpha_k in cells where species k is a trace.  Returns
+    (isolated, local): the largest |A - B| / |B| over trace cells whose
+    7-cell reach (the two faces' stencils, +-3 in every direction) holds no
+    cell where k is above TRACE, and the largest |A - B| / max |B| over that
+    reach for trace cells next to a material interface, where the trace
+    value is a small difference of bulk-sized terms (a rounding of those
+    terms moves it in absolute, not relative, terms)."""
+    from scipy.ndimage import maximum_filter
+    IA = N + D + 1
+    shape = B.shape[1:]
+    al = [B[IA + k] for k in range(N - 1)]
+    al.append(1.0 - sum(al))
+    size = tuple(7 if n > 1 else 1 for n in shape)
+    iso, loc = 0.0, 0.0
+    for k in range(N):
+        trace = al[k] < TRACE
+        if not trace.any():
+            continue
+        isolated = trace & (maximum_filter(al[k], size=size, mode="nearest") < TRACE)
+        near = trace & ~isolated
+        comps = [k] + ([IA + k] if k < N - 1 else [])
+        for c in comps:
+            d = np.abs(A[c] - B[c])
+            if isolated.any():
+                iso = max(iso, float((d[isolated] / np.maximum(np.abs(B[c][isolated]), 1e-300)).max()))
+            if near.any():
+                reach = maximum_filter(np.abs(B[c]), size=size, mode="nearest")
+                loc = max(loc, float((d[near] / np.maximum(reach[near], 1e-300)).max()))
+    return iso, loc
+
+
 def solver(H, prob, flags, W=None, params=None):
     hp = None
     if params:
@@ -74,8 +119,12 @@ def check_stages(H, orc, prob, W0, flags=0, relax=True, tol=TOL, counters=True, 
         ref = o.stage(k, W0, Wo_s, dt, lam, relax=relax)
         got = s.stage(k, Wn, Ws)
         torch.cuda.synchronize()
-        err = rel_err(got.cpu().numpy(), ref, N, D, cmax)
+        g = got.cpu().numpy()
+        err = rel_err(g, ref, N, D, cmax)
+        iso, loc = trace_errors(g, ref, N, D)
+        print(f"{prob.name} stage {k}: max rel {err:.2e}; trace cells: isolated {iso:.2e}, near interfaces {loc:.2e}")
         assert err <= tol, (prob.name, k, err)
+        assert iso <= TRACE_ISOLATED and loc <= tol, (prob.name, k, iso, loc)
         # next stage from the oracle's output on both sides
         Wo_s = ref
         Ws = torch.from_numpy(ref).cuda()
@@ -357,9 +406,13 @@ def check_stages_first(H, orc, prob):
     H.hrm_reset_diagnostics(s.ctx)
     got = s.stage(0, s.W, s.W)
     torch.cuda.synchronize()
-    err = rel_err(got.cpu().numpy(), ref, N, D, cmax)
-    print(f"{prob.name} {prob.n}: stage 0 max rel {err:.2e}")
+    g = got.cpu().numpy()
+    err = rel_err(g, ref, N, D, cmax)
+    iso, loc = trace_errors(g, ref, N, D)
+    print(f"{prob.name} {prob.n}: stage 0 max rel {err:.2e}; trace cells: isolated {iso:.2e}, "
+          f"near interfaces {loc:.2e}")
     assert err <= TOL
+    assert iso <= TRACE_ISOLATED and loc <= TOL, (iso, loc)
     dg, co = s.diagnostics(), o.counter_dict()
     for key in ("alg1", "alg2", "interp_hs", "alg3", "alg4", "flux_hs", "relax_bad"):
         assert dg[key] == co[key], (key, dg[key], co[key])
@@ -471,6 +524,123 @@ def test_four_eq_wavespeed_parity(H, orc, maker):
     ref = o.max_wavespeed(W)
     assert np.allclose(ms, ref, rtol=1e-11, atol=0), (ms, ref)
     s.close()
+
+
+def _oracle_equilibrium(o, W):
+    """(p, T, c) of the HRM per cell from the oracle."""
+    M = W.shape[0]
+    flat = W.reshape(M, -1)
+    out = np.array([o.hrm_eos(flat[:, j]) for j in range(flat.shape[1])])
+    return out[:, 0], out[:, 1], out[:, 2]
+
+
+def _hrm_c_50_digits(eos, w, D):
+    """The HRM sound speed of eq:4_eqn_sos in 50-digit arithmetic: p* as the
+    positive root of the relaxation quadratic of Sec. 4.2, Psi_k and Gamma by
+    implicit differentiation of it at fixed e and fixed alpha_k rho_k."""
+    import mpmath as mp
+    mp.mp.dps = 50
+    N = eos.N
+    m = [mp.mpf(float(w[k])) for k in range(N)]
+    mom = [mp.mpf(float(w[N + d])) for d in range(D)]
+    E = mp.mpf(float(w[N + D]))
+    cv = [mp.mpf(float(x)) for x in eos.cv]
+    R = [mp.mpf(float(g)) * cv[k] - cv[k] for k, g in enumerate(eos.gamma)]
+    q = [mp.mpf(float(x)) for x in eos.q]
+    p1 = mp.mpf(float(eos.pinf[0]))
+    rho = sum(m)
+    e = (E - sum(x * x for x in mom) / (2 * rho)) / rho
+
+    def coeffs(mk, ev):
+        r = sum(mk)
+        Y = [x / r for x in mk]
+        A = sum(Y[k] * cv[k] for k in range(N))
+        G = sum(Y[k] * R[k] for k in range(N))
+        re = sum(mk[k] * (ev - q[k]) for k in range(N))
+        B = -(re * G - p1 * A - p1 * Y[0] * R[0])
+        C = -re * p1 * (G - Y[0] * R[0])
+        return A, B, C
+
+    def root(mk, ev):
+        A, B, C = coeffs(mk, ev)
+        d = mp.sqrt(B * B - 4 * A * C)
+        return (-B + d) / (2 * A) if B <= 0 else 2 * C / (-B - d)
+
+    p = root(m, e)
+    A, B, C = coeffs(m, e)
+    h = mp.mpf(10) ** -20
+    c2 = 0
+    for k in range(N):
+        mk = list(m)
+        mk[k] += h * rho
+        # Psi_k = dp/d(m_k) at fixed e: implicit derivative of A p^2 + B p + C = 0
+        Ap, Bp, Cp = coeffs(mk, e)
+        Psi = -((Ap - A) * p * p + (Bp - B) * p + (Cp - C)) / (h * rho) / (2 * A * p + B)
+        c2 += m[k] / rho * Psi
+    Ae, Be, Ce = coeffs(m, e + h * e)
+    Gam = -((Be - B) * p + (Ce - C)) / (h * e) / (2 * A * p + B) / rho
+    c2 += Gam * p / rho
+    return float(p), float(mp.sqrt(c2))
+
+
+@pytest.mark.parametrize("kind", ["random_two", "random_three", "config2_developed", "acoustic"])
+def test_equilibrium_state_parity(H, orc, kind):
+    """Per-cell HRM state (Sec. 3): p* and T* of the relaxation against the
+    oracle to 1e-11, and the HRM sound speed of eq:4_eqn_sos.  p* is
+    ill-conditioned in a liquid at low pressure (its relative error in
+    double grows like gamma_1 p_inf,1 / p times the rounding of rho e-tilde,
+    up to ~1e-8 here), and device and oracle share that error (their p* agree
+    to the bit).  c inherits it: against a 50-digit evaluation of the
+    printed formula (exact p*, implicit derivatives) each side's c must lie
+    within 1e-11 + 2 e_p, e_p the relative error of the double p* of the
+    cell; the device's closed form and the oracle's printed quotient then
+    agree within 1e-11 + 4 e_p."""
+    if kind.startswith("random"):
+        eos = I.eos_of(I.LIQ_A, I.AIR) if kind == "random_two" else I.eos_of(I.LIQ_B, I.AIR, I.HELIUM)
+        n = (20, 15)
+        W = I.random_admissible(eos, 2, n[0] * n[1], seed=77, p_range=(1e3, 1e10), u_scale=300.0)
+        W = np.ascontiguousarray(W.reshape(W.shape[0], 1, n[1], n[0]))
+        prob = I.Problem("random", eos, 2, n, (1e-3, 1e-3), [(0, 0), (0, 0)], W)
+    elif kind == "config2_developed":
+        prob = I.config2(64, 32)
+        prob.W = developed(orc, prob, 3)
+    else:
+        prob = I.acoustic_1d(400)
+    o = orc.from_problem(prob)
+    s = solver(H, prob, H.FUSE_RELAX, W=prob.W)
+    p, T, c = (a.ravel() for a in s.equilibrium())
+    s.close()
+    po, To, co = _oracle_equilibrium(o, prob.W)
+    assert np.isfinite(p).all() and np.isfinite(c).all()
+    ep = np.abs(p - po) / po
+    eT = np.abs(T - To) / To
+    flat = prob.W.reshape(prob.M, -1)
+    ncell = flat.shape[1]
+    idx = np.arange(ncell) if ncell <= 400 else np.random.default_rng(5).choice(ncell, 400, replace=False)
+    ex = np.array([_hrm_c_50_digits(prob.eos, flat[:, j], prob.D) for j in idx])
+    e_p = np.abs(p[idx] - ex[:, 0]) / ex[:, 0]
+    e_dev = np.abs(c[idx] - ex[:, 1]) / ex[:, 1]
+    e_orc = np.abs(co[idx] - ex[:, 1]) / ex[:, 1]
+    ec = np.abs(c[idx] - co[idx]) / co[idx]
+    print(f"{kind}: p* vs oracle max rel {ep.max():.2e}, T* {eT.max():.2e}; double p* vs 50 digits up to "
+          f"{e_p.max():.2e}; c_HRM vs 50 digits: device {e_dev.max():.2e}, oracle {e_orc.max():.2e} "
+          f"(beyond 2 e_p: {(e_dev - 2 * e_p).max():.2e}, {(e_orc - 2 * e_p).max():.2e}); device vs oracle "
+          f"max {ec.max():.2e}, median {np.median(ec):.2e}")
+    assert ep.max() <= 1e-11 and eT.max() <= 1e-11
+    assert (e_dev <= 1e-11 + 2.0 * e_p).all() and (e_orc <= 1e-11 + 2.0 * e_p).all()
+    assert (ec <= 1e-11 + 4.0 * e_p).all()
+
+
+def test_equilibrium_state_of_inadmissible_cells_is_nan(H):
+    """A cell with rho(e - qbar) < 0 has no relaxed state: NaN in all three."""
+    prob = I.config1(64)
+    W = prob.W.copy()
+    W[prob.N + prob.D, 0, 0, 5] = -1.0
+    s = solver(H, prob, H.FUSE_RELAX, W=W)
+    p, T, c = s.equilibrium()
+    s.close()
+    assert np.isnan(p[0, 0, 5]) and np.isnan(T[0, 0, 5]) and np.isnan(c[0, 0, 5])
+    assert np.isfinite(np.delete(c.ravel(), 5)).all()
 
 
 # ------------------------------------------------------------------ Dirichlet sides

@@ -19,13 +19,3 @@ def test_bitwise_max_of_wavespeeds():
     # |u| + c is never -0: +0 + -0 is +0 under round-to-nearest
     assert np.signbit(np.float64(0.0) + np.float64(-0.0)) == False  # noqa: E712
 
-
-def test_slot_count_is_a_power_of_two_covered_by_the_blocks():
-    """Slots: the largest power of two up to min(blocks, 2048); block b goes
-    to slot b & (S - 1), so blocks 0 .. S-1 reach every slot."""
-    for nblk in (1, 2, 3, 7, 8, 80, 1000, 2048, 2240, 73728):
-        S = 1
-        while S < 2048 and 2 * S <= nblk:
-            S *= 2
-        assert S & (S - 1) == 0 and S <= min(nblk, 2048) and (2 * S > min(nblk, 2048))
-        assert set(b & (S - 1) for b in range(nblk)) == set(range(S))

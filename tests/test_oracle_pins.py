@@ -962,3 +962,21 @@ def test_mlp_zero_network_fifth_order_in_the_solver(orc):
         err.append(np.abs(W[pr.N + pr.D + 1, 0] - ex).mean())
     order = np.log2(err[0] / err[1])
     assert 4.7 < order < 5.3, (err, order)
+
+
+def test_stored_exact_profiles_are_the_exact_solution():
+    """The stored exact density profiles of the shock tube at 240 us (the
+    reference of the learned-weight L1 errors the benchmark reports) equal
+    the exact stiffened-gas Riemann solution sampled at the cell centres."""
+    import os
+    from oracle import exact_riemann as ER
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    L = dict(rho=1000.0, u=0.0, p=1e9, gamma=4.4, pinf=6e8)
+    R = dict(rho=50.0, u=0.0, p=1e5, gamma=1.4, pinf=0.0)
+    for n in (400, 2048):
+        stored = np.loadtxt(os.path.join(here, f"exact_rho_shock_tube_{n}.txt"))
+        x = (np.arange(n) + 0.5) / n
+        rho, _, _ = ER.solve(x, 240e-6, 0.7, L, R)
+        assert np.array_equal(stored, rho)
+        prob = I.config1(n)
+        assert prob.eos.gamma[0] == L["gamma"] and prob.eos.pinf[0] == L["pinf"] and prob.t_end == 240e-6

@@ -343,32 +343,47 @@ def bench_learned(args):
     from paper_2208_04488_amd import hrm, learned
     from paper_2208_04488_amd import inputs as I
 
-    t0 = time.perf_counter()
-    fine = learned.fine_ensemble(nprob=1024, nmin=100, nmax=1000, seed=4001)
-    X, T = learned.training_data(fine, snapshots=(40, 120))
     prior = learned.init_params(0, last_scale=0.0)
-    loss0 = learned.mean_loss(prior, X, T)
-    params, _ = learned.train(X, T, steps=3000, count=16384, lr=2e-3, seed=0)
-    loss1 = learned.mean_loss(params, X, T)
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
-    npairs = X.shape[0]
-    del X, T
+    sources = {}
+    # the same label recipe (injection from a twice finer grid) on two sources:
+    # fine 1D Riemann problems of the batched workload's kind, and lines of
+    # the 3D multimode workload at 256^3 (every 8th line in each direction)
+    for src in ("ensemble_1d", "multimode_3d"):
+        t0 = time.perf_counter()
+        if src == "ensemble_1d":
+            fine = learned.fine_ensemble(nprob=1024, nmin=100, nmax=1000, seed=4001)
+            X, T = learned.training_data(fine, snapshots=(40, 120))
+            data = "1024 fine 1D two-phase Riemann problems (200-2000 cells) after 40 and 120 FP64 steps"
+        else:
+            X, T = learned.training_data_grid(I.config3(args.n3d), snapshots=(60, 120), stride=8)
+            data = (f"lines of the {args.n3d}^3 multimode workload (every 8th in each transverse direction, all "
+                    f"three directions) after 60 and 120 FP64 steps")
+        loss0 = learned.mean_loss(prior, X, T)
+        params, _ = learned.train(X, T, steps=3000, count=16384, lr=2e-3, seed=0)
+        loss1 = learned.mean_loss(params, X, T)
+        torch.cuda.synchronize()
+        sources[src] = dict(params=params, pairs=int(X.shape[0]), seconds=time.perf_counter() - t0,
+                            loss_prior=loss0, loss_trained=loss1, data=data + ", labels by injection")
+        del X, T
+        torch.cuda.empty_cache()
 
     stream = torch.cuda.current_stream()
     out = {"workload": f"planar two-phase shock tube (liquid 1e9 Pa | air 1e5 Pa at x = 0.7), "
                        f"{args.learned_nx}x{args.learned_ny} cells, 2 species, transmissive x / periodic y, "
                        f"CFL 0.4, to 240 us",
            "envelope": "learned weights: FP64 face arithmetic, one and two dimensions only",
-           "training": {"pairs": npairs, "adam_steps": 3000, "minibatch": 16384, "seconds": train_s,
-                        "loss_prior": loss0, "loss_trained": loss1,
-                        "data": "1024 fine 1D two-phase Riemann problems (200-2000 cells) after 40 and 120 FP64 "
-                                "steps, labels by injection"}}
-    legs = (("plain", None), ("prior", prior), ("learned", params))
+           "training": {k: {kk: vv for kk, vv in v.items() if kk != "params"} | {"adam_steps": 3000,
+                                                                                "minibatch": 16384}
+                        for k, v in sources.items()},
+           "shipped_weights": "learned = trained on the 1D ensemble; learned_3d = trained on 3D multimode lines"}
+    legs = (("plain", None), ("prior", prior), ("learned", sources["ensemble_1d"]["params"]),
+            ("learned_3d", sources["multimode_3d"]["params"]))
     # the 1D workload at its own size, to 240 us (cheap; context for the 2D one)
     p1 = I.config1(400)
     ex1 = exact_profile(400)
     for name, mlp in legs:
+        if args.learned_no_l1:
+            break
         s = hrm.Solver(p1, flags=hrm.FUSE_RELAX, mlp=mlp)
         k = run_to_end(s, p1, 100)
         w = s.state()
@@ -383,20 +398,20 @@ def bench_learned(args):
         s.advance(args.warmup, cfl=prob.cfl)
         ms, _ = timed_advance(s, args.learned_steps, prob.cfl, stream)
         tm = sweep_timers(s, 5, prob.cfl)
-        steps = args.warmup + args.learned_steps + 5 + run_to_end(s, prob, 200)
+        steps = args.warmup + args.learned_steps + 5 + (0 if args.learned_no_l1 else run_to_end(s, prob, 200))
         d = s.diagnostics()
         w = s.state()
         s.close()
-        rho = w[:N].sum(axis=0)
+        rho = w[:N].sum(axis=0).reshape(-1, prob.n[0])  # rows of the planar problem
         leg = {"value": prob.ncell * args.learned_steps / (ms * 1e-3), "unit": "cell-updates/s",
                "ms_per_step": ms / args.learned_steps,
                "sweep_ms_per_launch": {k: tm[k][0] / max(tm[k][1], 1) for k in ("sweep_x", "sweep_y")},
                "relax_bad": d["relax_bad"], "steps_to_end": steps,
                "rows_identical": bool(np.abs(rho - rho[0]).max() <= 1e-9 * rho.max())}
-        if ex is not None:
+        if ex is not None and not args.learned_no_l1:
             leg["l1_rho_vs_exact"] = float(np.abs(rho[0] - ex).sum() * prob.dx[0])
         out[name] = leg
-    for name in ("prior", "learned"):
+    for name in ("prior", "learned", "learned_3d"):
         out[name]["speedup_vs_plain"] = out[name]["value"] / out["plain"]["value"]
     faces = (prob.n[0] + 1) * prob.n[1] + prob.n[0] * (prob.n[1] + 1)
     mf = 3 * faces * 2 * M * MLP_FLOPS_PER_STENCIL  # 2M stencils per face, both sweeps, 3 stages
@@ -504,6 +519,10 @@ def main():
                     help="timed steps of the learned-weight comparison (0 skips it)")
     ap.add_argument("--learned-nx", type=int, default=2048)
     ap.add_argument("--learned-ny", type=int, default=1024)
+    ap.add_argument("--learned-no-l1", action="store_true",
+                    help="time the learned legs only (no runs to 240 us; for profiling)")
+    ap.add_argument("--only-2d", action="store_true",
+                    help="run the 2D liquid column leg alone (for profiling its kernels)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 2 GiB elementwise copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -527,6 +546,10 @@ def main():
         return
     from paper_2208_04488_amd import inputs as I
 
+    if args.only_2d:
+        print(json.dumps({"liquid_column_2d": bench_grid(I.config2(args.nx, args.ny), args, args.total2d)}),
+              flush=True)
+        return
     prob = I.config3(args.n3d)
     N, D, M = prob.N, prob.D, prob.M
     g = bench_grid(prob, args, args.total3d, counters_file="k_sweep_multimode_256cube_fp64_counters.json")

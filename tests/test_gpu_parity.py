@@ -394,14 +394,34 @@ def test_full_size_multimode_3d_stage(H, orc):
     check_stages_first(H, orc, prob)
 
 
-def check_stages_first(H, orc, prob):
+def test_full_size_multimode_3d_developed(H, orc):
+    """The 3D multimode workload run on the GPU to steps 100 and 200 (its
+    length): at each, one full-grid SSP-RK3 stage from the GPU's state on
+    both sides, every cell compared with the oracle."""
+    import torch
+    prob = I.config3(256)
+    s = solver(H, prob, H.FUSE_RELAX)
+    done = 0
+    for k in (100, 200):
+        s.advance(k - done, cfl=prob.cfl)
+        done = k
+        torch.cuda.synchronize()
+        assert s.diagnostics()["relax_bad"] == 0
+        W = s.state()
+        print(f"after {k} steps (t = {s.slot[4].item():.4e} s):", end=" ")
+        check_stages_first(H, orc, prob, W)
+    s.close()
+
+
+def check_stages_first(H, orc, prob, W0=None):
     import torch
     N, D = prob.N, prob.D
+    W0 = prob.W if W0 is None else W0
     o = orc.from_problem(prob)
-    dt, lam = o.dt(prob.W, prob.cfl)
-    cmax = o.max_wavespeed(prob.W).max()
-    ref = o.stage(0, prob.W, prob.W, dt, lam)
-    s = solver(H, prob, H.FUSE_RELAX)
+    dt, lam = o.dt(W0, prob.cfl)
+    cmax = o.max_wavespeed(W0).max()
+    ref = o.stage(0, W0, W0, dt, lam)
+    s = solver(H, prob, H.FUSE_RELAX, W=W0)
     s.set_slot(dt, lam)
     H.hrm_reset_diagnostics(s.ctx)
     got = s.stage(0, s.W, s.W)

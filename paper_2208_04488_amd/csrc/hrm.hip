@@ -184,18 +184,16 @@ __global__ void __launch_bounds__(BS* BA, SWEEP_WAVES) k_sweep(const SweepArgs A
     __syncthreads();
 
     // one face per thread: between sweep nodes c0-1+ts and c0+ts
-    unsigned cnt[C_N] = {0, 0, 0, 0, 0, 0, 0};
+    unsigned cnt = 0;  // packed counts (cnt_one)
     double G[M], Gp[NA];
     {
-        unsigned lc[C_N] = {0, 0, 0, 0, 0, 0, 0};
+        unsigned lc = 0;
         face_flux<N, D, DIR, NS, FS, R, WT>(lds + base(ta, ts), A.e, A.P, A.slot[1 + DIR], G, Gp, lc);
         // face c0+ts is counted once: the last face of a tile is the first
         // face of the next tile unless it is the boundary face nsw
         const int f = c0 + ts;
         const bool ok = f <= nsw && (ts < BS - 1 || f == nsw) && (abase + ta < na);
-        if (ok)
-#pragma unroll
-            for (int k = 0; k < C_N; ++k) cnt[k] += lc[k];
+        if (ok) cnt = lc;
     }
     // A middle direction only adds to the right-hand side (MODE_ADD): its
     // cell's accumulated values are loaded here, before the barriers, so that
@@ -260,7 +258,7 @@ __global__ void __launch_bounds__(BS* BA, SWEEP_WAVES) k_sweep(const SweepArgs A
                     const double Lc = D > 1 ? A.rhs[c * nc + cell] + L[c] : L[c];
                     w[c] = A.a * A.Wn[c * nc + cell] + A.b * (A.Ws[c * nc + cell] + dt * Lc);
                 }
-                if (A.relax && !relax_cell<N, D>(A.e, w)) cnt[C_RELAX_BAD]++;
+                if (A.relax && !relax_cell<N, D>(A.e, w)) cnt += cnt_one(C_RELAX_BAD);
             }
 #pragma unroll
             for (int c = 0; c < M; ++c) A.Wout[c * nc + cell] = w[c];

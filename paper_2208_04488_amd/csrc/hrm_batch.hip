@@ -145,12 +145,12 @@ __global__ void __launch_bounds__(BS, 3) k_batch(const BatchArgs A)
                     __syncthreads();
                     double G[M], Gp[NA];
                     {
-                        unsigned lc[C_N] = {0, 0, 0, 0, 0, 0, 0};
+                        unsigned lc = 0;  // packed counts of this face (cnt_one)
                         face_flux<N, D, 0, 1, FS, R, 0, false>(lds + ts, e, P, lam, G, Gp, lc);
                         const int f = c0 + ts;  // counted once, as in k_sweep
                         if (f <= n && (ts < BS - 1 || f == n))
 #pragma unroll
-                            for (int k = 0; k < C_N; ++k) cnt[k] += lc[k];
+                            for (int k = 0; k < C_N; ++k) cnt[k] += cnt_get(lc, k);
                     }
                     __syncthreads();
 #pragma unroll

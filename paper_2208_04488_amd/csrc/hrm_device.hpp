@@ -48,6 +48,13 @@ struct ParDev {
 // counters accumulated per thread, flushed once per wave
 enum { C_ALG1 = 0, C_ALG2, C_IHS, C_ALG3, C_ALG4, C_FHS, C_RELAX_BAD, C_N };
 
+// The counts of one face (and one cell update) packed into one register, 4
+// bits per counter: a face blends at most 2N <= 6 partial densities (Alg. 1)
+// and 2 volume-fraction sets (Alg. 2), switches at most twice, limits its
+// flux once.  One register instead of seven live through the face.
+constexpr unsigned cnt_one(int k) { return 1u << (4 * k); }
+__device__ inline unsigned cnt_get(unsigned packed, int k) { return (packed >> (4 * k)) & 15u; }
+
 // A full state: conservative and primitive slots side by side.
 template <int N, int D, typename R = double>
 struct St {
@@ -362,7 +369,7 @@ __device__ inline double lim_theta(double a, double b, double eps)
 // On return V is a complete state (conservative slots, rho, c, rho c^2).
 template <int N, int D, typename R>
 __device__ inline void interp_limit(const EosDev& e, const ParDev& P, St<N, D, R>& V, const St<N, D, R>& node,
-                                    unsigned* cnt)
+                                    unsigned& cnt)
 {
 #pragma unroll
     for (int k = 0; k < N; ++k) {  // Alg. 1
@@ -371,7 +378,7 @@ __device__ inline void interp_limit(const EosDev& e, const ParDev& P, St<N, D, R
         if (b < m) {
             const double th = (a - m) / (a - b);
             V.ar[k] = (R)((1.0 - th) * a + th * b);
-            cnt[C_ALG1]++;
+            cnt += cnt_one(C_ALG1);
         }
     }
     double at[N], asum = 0.0;  // Alg. 2
@@ -387,7 +394,7 @@ __device__ inline void interp_limit(const EosDev& e, const ParDev& P, St<N, D, R
     if (th < 1.0) {
 #pragma unroll
         for (int k = 0; k < N - 1; ++k) V.al[k] = (1.0 - th) * node.al[k] + th * V.al[k];
-        cnt[C_ALG2]++;
+        cnt += cnt_one(C_ALG2);
     }
     // hard switch, judged on the completed limited state
     complete_from_prim<N, D, R>(e, V);
@@ -410,7 +417,7 @@ __device__ inline void interp_limit(const EosDev& e, const ParDev& P, St<N, D, R
 #pragma unroll
         for (int k = 0; k < N - 1; ++k) V.al[k] = node.al[k];
         complete_from_prim<N, D, R>(e, V);
-        cnt[C_IHS]++;
+        cnt += cnt_one(C_IHS);
     }
 }
 
@@ -492,7 +499,7 @@ __device__ inline bool flux_limit_clean(const EosDev& e, const ParDev& P, const 
 template <int N, int D, int DIR>
 __device__ inline void flux_limit(const EosDev& e, const ParDev& P, const St<N, D>& L, const St<N, D>& R,
                                   double lam, const double* Gho, const double* Gho_p, const double* Glo,
-                                  const double* Glo_p, double* G, double* Gp, unsigned* cnt)
+                                  const double* Glo_p, double* G, double* Gp, unsigned& cnt)
 {
     constexpr int M = 2 * N + D, IE = N + D, IA = N + D + 1;
     double WL[M], WR[M], FL[M], FR[M];
@@ -560,7 +567,7 @@ __device__ inline void flux_limit(const EosDev& e, const ParDev& P, const St<N, 
             th = fmin(th, lim_theta(am_lo[k], am[k], P.eps_f_a));
         }
     }
-    if (th < 1.0) cnt[C_ALG3]++;
+    if (th < 1.0) cnt += cnt_one(C_ALG3);
     // When Alg. 3 leaves theta = 1, G* = G^ho and W* = W^ho exactly.  If Alg. 4
     // also gives 1 and everything is finite, the hard switch cannot fire
     // (eps >= eps^HS, checked at context creation), so G** = G^ho: return
@@ -596,7 +603,7 @@ __device__ inline void flux_limit(const EosDev& e, const ParDev& P, const St<N, 
     }
     const double th2 = fmin(lim_theta(rep_lo, rhoe_tilde<N, D>(e, Wp), P.eps_f_re),
                             lim_theta(rem_lo, rhoe_tilde<N, D>(e, Wm), P.eps_f_re));
-    if (th2 < 1.0) cnt[C_ALG4]++;
+    if (th2 < 1.0) cnt += cnt_one(C_ALG4);
 #pragma unroll
     for (int c = 0; c < M; ++c) G[c] = (1.0 - th2) * Glo[c] + th2 * Gs[c];
 #pragma unroll
@@ -629,7 +636,7 @@ __device__ inline void flux_limit(const EosDev& e, const ParDev& P, const St<N, 
     hs |= rep < fmin(P.hs_f_re, rep_lo);
     hs |= rem < fmin(P.hs_f_re, rem_lo);
     if (hs) {
-        cnt[C_FHS]++;
+        cnt += cnt_one(C_FHS);
 #pragma unroll
         for (int c = 0; c < M; ++c) G[c] = Glo[c];
 #pragma unroll
@@ -648,6 +655,9 @@ __device__ inline int map_bc(int g, int n, int lo, int hi)
     return g;
 }
 
+// the packed counts of a thread (cnt_one), summed over the wave as below
+__device__ inline void flush_counters(unsigned packed, unsigned long long* dst);
+
 // sum each counter over the wave, one atomic per non-zero counter.  Most
 // counters are zero on every lane of most waves: a ballot skips those (the
 // branch is wave-uniform), and the others are summed in 32 bits (a lane's
@@ -663,6 +673,15 @@ __device__ inline void flush_counters(const unsigned* c, unsigned long long* dst
         for (int off = 32; off > 0; off >>= 1) v += __builtin_amdgcn_ds_bpermute((lane ^ off) << 2, v);
         if (lane == 0) atomicAdd(&dst[k], (unsigned long long)(unsigned)v);
     }
+}
+
+__device__ inline void flush_counters(unsigned packed, unsigned long long* dst)
+{
+    if (__ballot(packed != 0u) == 0ull) return;
+    unsigned c[C_N];
+#pragma unroll
+    for (int k = 0; k < C_N; ++k) c[k] = cnt_get(packed, k);
+    flush_counters(c, dst);
 }
 
 // NaN-propagating max (a NaN anywhere makes the result NaN)

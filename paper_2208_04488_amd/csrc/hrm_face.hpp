@@ -99,8 +99,9 @@ __device__ inline R sensor_ratio_t(R v0, R v1, R v2, R v3, R v4)
 // a call would spill the whole face state around it.
 template <int N, int D, int DIR, int NS, int FS, typename R, int WT = 0, bool LOW = true>
 __device__ __forceinline__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, double lam, double* G, double* Gp,
-                          unsigned* cnt)
+                          unsigned& cnt)
 {
+    static_assert(2 * N <= 15, "per-face counts are packed 4 bits per counter");
     using F = NodeFields<N, D>;
     constexpr int M = 2 * N + D, IE = N + D, IA = N + D + 1;
     constexpr int NA = N > 1 ? N - 1 : 1;

@@ -94,18 +94,25 @@ __device__ inline unsigned long long wave_umax64(unsigned long long v)
 // together; 1D keeps the tiles on blockIdx.x, the dimension with room for
 // long lines.
 // The register budget of the sweeps is cut to three waves per SIMD (168
-// VGPRs).  For three species that spills ~200 bytes per lane, mostly around
-// the characteristic back-projection, but the third wave hides more LDS and
-// memory latency than the spills cost: 1024 x 512 step 0.441 -> 0.400 ms,
-// 256^3 FP64 +3 %, FP32 +11 %.  A fourth wave (128 VGPRs) spills more than
-// it hides: 1024 x 512 step 0.336 -> 0.347 ms, 256^3 FP64 -13 %.
-constexpr int SWEEP_WAVES = 3;
+// VGPRs): the third wave hides more LDS and memory latency than the spills
+// it causes cost (1024 x 512 step 0.441 -> 0.400 ms, 256^3 FP64 +3 %, FP32
+// +11 %).  A fourth wave (128 VGPRs) pays only where its workgroups' LDS
+// fits and the face keeps few values past the flux limiter's check: the
+// plain FP64 sweeps of 2D grids and the 3D x-sweep (1024 x 512 step -1.9 %,
+// 256^3 x-sweep -1.5 %).  In float it does not (256^3 x-sweep +3.5 %), and
+// the 3D y- and z-sweeps' 16 x 16 tiles (43 KB of LDS) fit only three
+// workgroups per CU.
+template <int D, int DIR, typename R, int WT>
+constexpr int sweep_waves()
+{
+    return sizeof(R) == sizeof(double) && WT == 0 && (D == 2 || (D == 3 && DIR == 0)) ? 4 : 3;
+}
 
 // WS: the launch is a stage update that also folds the wavespeed maxima of
 // its output into A.wpart; a separate instantiation, so that the other
 // launches keep their register allocation
 template <int N, int D, int DIR, int BS, int BA, typename R, int WT, bool WS = false>
-__global__ void __launch_bounds__(BS* BA, SWEEP_WAVES) k_sweep(const SweepArgs A)
+__global__ void __launch_bounds__(BS* BA, (sweep_waves<D, DIR, R, WT>())) k_sweep(const SweepArgs A)
 {
     using F = NodeFields<N, D>;
     constexpr int M = 2 * N + D, IA = N + D + 1;

@@ -571,7 +571,7 @@ def main():
         "wall_s_timed": f64["wall_s_timed"],
         "positivity": f64["positivity"],
         "fp32": g["fp32"],
-        "tiles": "grid sweeps: fixed tiles (x 64x4, y and z 16x16); the ensemble's launch shape is autotuned",
+        "tiles": "grid sweeps: x 64x4, or 32x8 where it needs fewer face threads (256^3: 32x8); y and z 16x16; the ensemble's launch shape is autotuned",
     }
     if args.total2d > 0:
         p2 = I.config2(args.nx, args.ny)

@@ -593,15 +593,23 @@ struct TimerScope {
     }
 };
 
-// tile of the sweep in direction dir: BS face threads along it, BA across
-void sweep_tile(int D, int dir, int& BS, int& BA)
+// tile of the sweep in direction dir: BS face threads along it, BA across.
+// A tile computes BS faces for BS - 1 cells, so a line of n cells takes
+// ceil(n / (BS - 1)) tiles.  Along x (2D, 3D) the 64 x 4 tile gives way to
+// 32 x 8 where that needs fewer face threads for the line: a 256-cell line
+// takes 5 tiles of 64 (320 face threads, the last tile 4 cells) or 9 of 32
+// (288).  Learned weights keep 64 x 4.
+void sweep_tile(const hrm_ctx* c, int dir, int& BS, int& BA)
 {
-    if (D == 1) {
+    if (c->D == 1) {
         BS = 256;
         BA = 1;
     } else if (dir == 0) {
-        BS = 64;
-        BA = 4;
+        const long long n = c->n[0];
+        const bool narrow = c->weights != HRM_WEIGHTS_MLP && (n + 30) / 31 * 32 < (n + 62) / 63 * 64 &&
+                            (n + 30) / 31 <= 65535;  // tiles along x ride on blockIdx.y
+        BS = narrow ? 32 : 64;
+        BA = narrow ? 8 : 4;
     } else {
         BS = 16;
         BA = 16;
@@ -644,8 +652,9 @@ struct Ops {
     template <int DIR, int BS, int BA, bool WS>
     static void launch_kernel(hrm_ctx* c, const hrm::SweepArgs& A, dim3 grd, dim3 blk, hipStream_t s)
     {
-        if constexpr (D <= 2) {
-            // learned weights: FP64 face arithmetic, one and two dimensions
+        if constexpr (D <= 2 && !(DIR == 0 && BS == 32)) {
+            // learned weights: FP64 face arithmetic, one and two dimensions,
+            // on the 64 x 4 x-tile (sweep_tile)
             if (c->weights == HRM_WEIGHTS_MLP) {
                 hipLaunchKernelGGL((hrm::k_sweep<N, D, DIR, BS, BA, double, 1, WS>), grd, blk, 0, s, A);
                 return;
@@ -663,7 +672,14 @@ struct Ops {
         if constexpr (D == 1) {
             launch_dir<0, 256, 1>(c, A, s);
         } else {
-            if (dir == 0) launch_dir<0, 64, 4>(c, A, s);
+            if (dir == 0) {
+                int BS, BA;
+                sweep_tile(c, 0, BS, BA);
+                if (BS == 32)
+                    launch_dir<0, 32, 8>(c, A, s);
+                else
+                    launch_dir<0, 64, 4>(c, A, s);
+            }
             if (dir == 1) launch_dir<1, 16, 16>(c, A, s);
             if constexpr (D >= 3)
                 if (dir == 2) launch_dir<2, 16, 16>(c, A, s);
@@ -924,7 +940,7 @@ int hrm_create(const hrm_grid* g, const hrm_eos* e, const hrm_params* prm, hrm_c
     for (int d = 0; d < c->D; ++d) {
         // every sweep launch within the grid limits (y and z at most 65535 blocks)
         int BS, BA;
-        sweep_tile(c->D, d, BS, BA);
+        sweep_tile(c, d, BS, BA);
         const dim3 gd = sweep_grid(c, d, BS, BA);
         if (gd.y > 65535u || gd.z > 65535u) {
             delete c;
@@ -973,7 +989,7 @@ int hrm_create(const hrm_grid* g, const hrm_eos* e, const hrm_params* prm, hrm_c
     c->npart = (int)std::min<long long>((c->ncell + 255) / 256, 2048);
     {
         int BS, BA;
-        sweep_tile(c->D, c->D - 1, BS, BA);
+        sweep_tile(c, c->D - 1, BS, BA);
         const dim3 g = sweep_grid(c, c->D - 1, BS, BA);
         // the largest power of two up to the block count and 2048, so that
         // every slot receives at least one block

@@ -327,7 +327,8 @@ def test_stage_parity_rough(H, orc, D, n):
 
 
 # degenerate and just-past-a-tile extents in 2D and 3D (x tiles hold 63 cells,
-# y and z tiles 15), transmissive and periodic
+# or 31 where that takes fewer face threads, as for 1..31 and 64 cells; y and
+# z tiles 15), transmissive and periodic
 @pytest.mark.parametrize("n,bc", [((1, 1), 0), ((1, 1), 1), ((2, 3), 0), ((3, 1), 1), ((1, 5), 0), ((64, 2), 1),
                                   ((2, 16), 0), ((3, 17), 1), ((1, 1, 1), 0), ((2, 1, 3), 1), ((3, 16, 2), 0),
                                   ((2, 2, 16), 1)])

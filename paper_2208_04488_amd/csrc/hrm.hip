@@ -98,14 +98,22 @@ __device__ inline unsigned long long wave_umax64(unsigned long long v)
 // it causes cost (1024 x 512 step 0.441 -> 0.400 ms, 256^3 FP64 +3 %, FP32
 // +11 %).  A fourth wave (128 VGPRs) pays only where its workgroups' LDS
 // fits and the face keeps few values past the flux limiter's check: the
-// plain FP64 sweeps of 2D grids and the 3D x-sweep (1024 x 512 step -1.9 %,
-// 256^3 x-sweep -1.5 %).  In float it does not (256^3 x-sweep +3.5 %), and
-// the 3D y- and z-sweeps' 16 x 16 tiles (43 KB of LDS) fit only three
-// workgroups per CU.
+// plain FP64 sweeps of 2D grids, the 3D x-sweep (1024 x 512 step -1.9 %,
+// 256^3 x-sweep -1.5 %) and the 3D z-sweep, which reads three arrays per
+// cell after its barriers (-5 %).  The z-sweep's 16 x 16 tile fits four
+// workgroups per CU only with the slim node record (rho formed again where
+// read); the y-sweep gained nothing from the same and keeps three.  In float
+// a fourth wave does not pay (256^3 x-sweep +3.5 %).
+template <int D, int DIR, typename R, int WT>
+constexpr bool sweep_slim()
+{
+    return sizeof(R) == sizeof(double) && WT == 0 && D == 3 && DIR == 2;
+}
+
 template <int D, int DIR, typename R, int WT>
 constexpr int sweep_waves()
 {
-    return sizeof(R) == sizeof(double) && WT == 0 && (D == 2 || (D == 3 && DIR == 0)) ? 4 : 3;
+    return sizeof(R) == sizeof(double) && WT == 0 && (D == 2 || (D == 3 && DIR != 1)) ? 4 : 3;
 }
 
 // WS: the launch is a stage update that also folds the wavespeed maxima of
@@ -114,7 +122,8 @@ constexpr int sweep_waves()
 template <int N, int D, int DIR, int BS, int BA, typename R, int WT, bool WS = false>
 __global__ void __launch_bounds__(BS* BA, (sweep_waves<D, DIR, R, WT>())) k_sweep(const SweepArgs A)
 {
-    using F = NodeFields<N, D>;
+    constexpr bool SLIM = sweep_slim<D, DIR, R, WT>();
+    using F = NodeFields<N, D, SLIM>;
     constexpr int M = 2 * N + D, IA = N + D + 1;
     constexpr int NA = N > 1 ? N - 1 : 1;
     constexpr int LN = BS + 5;
@@ -183,7 +192,7 @@ __global__ void __launch_bounds__(BS* BA, (sweep_waves<D, DIR, R, WT>())) k_swee
 #pragma unroll
         for (int d = 0; d < D; ++d) lds[(F::U + d) * FS + b] = s.u[d];
         lds[F::P * FS + b] = s.p;
-        lds[F::RHO * FS + b] = s.rho;
+        if constexpr (!SLIM) lds[F::RHO * FS + b] = s.rho;
         lds[F::C * FS + b] = s.c;
         lds[F::RC2 * FS + b] = s.rc2;
     }
@@ -195,7 +204,7 @@ __global__ void __launch_bounds__(BS* BA, (sweep_waves<D, DIR, R, WT>())) k_swee
     double G[M], Gp[NA];
     {
         unsigned lc = 0;
-        face_flux<N, D, DIR, NS, FS, R, WT>(lds + base(ta, ts), A.e, A.P, A.slot[1 + DIR], G, Gp, lc);
+        face_flux<N, D, DIR, NS, FS, R, WT, true, SLIM>(lds + base(ta, ts), A.e, A.P, A.slot[1 + DIR], G, Gp, lc);
         // face c0+ts is counted once: the last face of a tile is the first
         // face of the next tile unless it is the boundary face nsw
         const int f = c0 + ts;

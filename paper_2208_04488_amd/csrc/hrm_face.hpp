@@ -9,12 +9,16 @@
 namespace hrm {
 
 // LDS node record: the conservative vector W (M slots), then u_d (D),
-// p, rho, c, rho c^2.
-template <int N, int D>
+// p, rho, c, rho c^2.  The slim record leaves rho out (it is the sum of the
+// partial densities, formed again where it is read): one field less lets
+// the 3D z-sweep's 16 x 16 tiles fit four workgroups per CU.
+template <int N, int D, bool SLIM = false>
 struct NodeFields {
     static constexpr int M = 2 * N + D;
-    static constexpr int U = M, P = M + D, RHO = M + D + 1, C = M + D + 2, RC2 = M + D + 3;
-    static constexpr int COUNT = M + D + 4;
+    static constexpr bool slim = SLIM;
+    static constexpr int U = M, P = M + D, RHO = SLIM ? -1 : M + D + 1;
+    static constexpr int C = M + D + (SLIM ? 1 : 2), RC2 = C + 1;
+    static constexpr int COUNT = RC2 + 1;
 };
 
 // node j of the stencil, field f; NS = LDS stride between consecutive nodes,
@@ -25,10 +29,25 @@ __device__ inline double nodev(const double* nd, int j, int f)
     return nd[j * NS + f * FS];
 }
 
-template <int N, int D, int NS, int FS>
+// mixture density of node j: read, or in the slim record the sum of the
+// partial densities in the order the staging pass forms it (the same bits)
+template <class F, int N, int NS, int FS>
+__device__ inline double node_rho(const double* nd, int j)
+{
+    if constexpr (F::slim) {
+        double r = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) r += nodev<NS, FS>(nd, j, k);
+        return r;
+    } else {
+        return nodev<NS, FS>(nd, j, F::RHO);
+    }
+}
+
+template <int N, int D, int NS, int FS, bool SLIM>
 __device__ inline void load_node(const double* nd, int j, St<N, D>& s)
 {
-    using F = NodeFields<N, D>;
+    using F = NodeFields<N, D, SLIM>;
     constexpr int IE = N + D, IA = N + D + 1;
     double asum = 0.0;
 #pragma unroll
@@ -46,7 +65,7 @@ __device__ inline void load_node(const double* nd, int j, St<N, D>& s)
     }
     s.al[N - 1] = 1.0 - asum;
     s.p = nodev<NS, FS>(nd, j, F::P);
-    s.rho = nodev<NS, FS>(nd, j, F::RHO);
+    s.rho = node_rho<F, N, NS, FS>(nd, j);
     s.c = nodev<NS, FS>(nd, j, F::C);
     s.rc2 = nodev<NS, FS>(nd, j, F::RC2);
 }
@@ -97,12 +116,12 @@ __device__ inline R sensor_ratio_t(R v0, R v1, R v2, R v3, R v4)
 // are double.  LOW = false leaves out the first-order and direct-HRM branches
 // (selected by flags) for callers that never take them.  Always inlined:
 // a call would spill the whole face state around it.
-template <int N, int D, int DIR, int NS, int FS, typename R, int WT = 0, bool LOW = true>
+template <int N, int D, int DIR, int NS, int FS, typename R, int WT = 0, bool LOW = true, bool SLIM = false>
 __device__ __forceinline__ void face_flux(const double* nd, const EosDev& e, const ParDev& P, double lam, double* G, double* Gp,
                           unsigned& cnt)
 {
     static_assert(2 * N <= 15, "per-face counts are packed 4 bits per counter");
-    using F = NodeFields<N, D>;
+    using F = NodeFields<N, D, SLIM>;
     constexpr int M = 2 * N + D, IE = N + D, IA = N + D + 1;
     constexpr int NA = N > 1 ? N - 1 : 1;
     // FP32: the characteristic fields are interpolated as deviations from
@@ -123,8 +142,8 @@ __device__ __forceinline__ void face_flux(const double* nd, const EosDev& e, con
     // occupy registers across the whole face computation
     auto node_pair = [&](St<N, D>& a, St<N, D>& b) {
         asm volatile("" ::: "memory");
-        load_node<N, D, NS, FS>(nd, 2, a);
-        load_node<N, D, NS, FS>(nd, 3, b);
+        load_node<N, D, NS, FS, SLIM>(nd, 2, a);
+        load_node<N, D, NS, FS, SLIM>(nd, 3, b);
     };
 
     // first-order HLLC of the node pair and its quasi-conservative pair
@@ -161,7 +180,8 @@ __device__ __forceinline__ void face_flux(const double* nd, const EosDev& e, con
     R arb[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) arb[k] = (R)0.5 * (nv(2, k) + nv(3, k));
-    const R rb = (R)0.5 * (nv(2, F::RHO) + nv(3, F::RHO)), cb = (R)0.5 * (nv(2, F::C) + nv(3, F::C));
+    const R rb = (R)0.5 * ((R)node_rho<F, N, NS, FS>(nd, 2) + (R)node_rho<F, N, NS, FS>(nd, 3));
+    const R cb = (R)0.5 * (nv(2, F::C) + nv(3, F::C));
     // 1/(rho c), 1/(rho c^2) = rho (1/(rho c))^2 and 1/(2c) = rho/(2 rho c) from one
     // reciprocal (the means of two admissible nodes are positive)
     R irc;
@@ -241,7 +261,7 @@ __device__ __forceinline__ void face_flux(const double* nd, const EosDev& e, con
         double r[6], pr[6];
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
-            r[j] = nodev<NS, FS>(nd, j, F::RHO);
+            r[j] = node_rho<F, N, NS, FS>(nd, j);
             pr[j] = nodev<NS, FS>(nd, j, F::P);
         }
         const double sr = 0.5 * (sensor_ratio_t<double>(r[1], r[2], r[3], r[4], r[5]) +

@@ -96,24 +96,24 @@ __device__ inline unsigned long long wave_umax64(unsigned long long v)
 // The register budget of the sweeps is cut to three waves per SIMD (168
 // VGPRs): the third wave hides more LDS and memory latency than the spills
 // it causes cost (1024 x 512 step 0.441 -> 0.400 ms, 256^3 FP64 +3 %, FP32
-// +11 %).  A fourth wave (128 VGPRs) pays only where its workgroups' LDS
-// fits and the face keeps few values past the flux limiter's check: the
-// plain FP64 sweeps of 2D grids, the 3D x-sweep (1024 x 512 step -1.9 %,
-// 256^3 x-sweep -1.5 %) and the 3D z-sweep, which reads three arrays per
-// cell after its barriers (-5 %).  The z-sweep's 16 x 16 tile fits four
-// workgroups per CU only with the slim node record (rho formed again where
-// read); the y-sweep gained nothing from the same and keeps three.  In float
-// a fourth wave does not pay (256^3 x-sweep +3.5 %).
+// +11 %).  A fourth wave (128 VGPRs) pays for the plain FP64 sweeps once the
+// face keeps few values past the flux limiter's check, where the
+// workgroups' LDS fits: 1024 x 512 step -1.9 %, 256^3 x-sweep -1.5 %,
+// z-sweep (three arrays read per cell after its barriers) -5 %, y-sweep
+// -2 %.  The 3D y- and z-sweeps' 16 x 16 tiles fit four workgroups per CU
+// only with the slim node record (rho formed again where read, which costs
+// the x-sweep 2 % where its LDS fits anyway).  In float a fourth wave does
+// not pay (256^3 x-sweep +3.5 %).
 template <int D, int DIR, typename R, int WT>
 constexpr bool sweep_slim()
 {
-    return sizeof(R) == sizeof(double) && WT == 0 && D == 3 && DIR == 2;
+    return sizeof(R) == sizeof(double) && WT == 0 && D == 3 && DIR >= 1;
 }
 
 template <int D, int DIR, typename R, int WT>
 constexpr int sweep_waves()
 {
-    return sizeof(R) == sizeof(double) && WT == 0 && (D == 2 || (D == 3 && DIR != 1)) ? 4 : 3;
+    return sizeof(R) == sizeof(double) && WT == 0 && D >= 2 ? 4 : 3;
 }
 
 // WS: the launch is a stage update that also folds the wavespeed maxima of

@@ -11,7 +11,7 @@ namespace hrm {
 // LDS node record: the conservative vector W (M slots), then u_d (D),
 // p, rho, c, rho c^2.  The slim record leaves rho out (it is the sum of the
 // partial densities, formed again where it is read): one field less lets
-// the 3D z-sweep's 16 x 16 tiles fit four workgroups per CU.
+// the 3D y- and z-sweeps' 16 x 16 tiles fit four workgroups per CU.
 template <int N, int D, bool SLIM = false>
 struct NodeFields {
     static constexpr int M = 2 * N + D;

@@ -236,6 +236,14 @@ def bench_grid(prob, args, total_steps, counters_file=None):
                        "traffic_gbs": None if traffic is None else traffic / (ms_launch * 1e-3) / 1e9,
                        "algorithmic_bytes_per_launch": 8 * M * prob.ncell * sweep_arrays(D, kdir),
                        "flops_per_launch": flops, "ms_per_launch": ms_launch}
+    # every sweep against the same peak (the roofline object above is the
+    # sweep with the largest share of the step)
+    f64["sweep_fp64_fraction"] = {}
+    for d, nm in enumerate(names):
+        fl = mean_launch_flops(N, D, prob.n, d)
+        t_ms = f64["sweep_ms_per_launch"][nm]
+        f64["sweep_fp64_fraction"][nm] = {"tflops": fl / (t_ms * 1e-3) / 1e12,
+                                          "frac": fl / (t_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
     f64["hbm_gbs_algorithmic"] = algorithmic_bytes_per_cell_step(M) * f64["value"] / 1e9
     out["fp32"]["speedup_vs_fp64"] = out["fp32"]["value"] / f64["value"]
     steps = min(res["fp64"]["steps_run"], res["fp32"]["steps_run"])

@@ -573,6 +573,7 @@ def main():
                                f"periodic y/z, FP64 PP-WCNS-IS + thermal relaxation, CFL 0.4",
                    "cells": args.n3d ** 3, "species": N, "dim": D, "components": M},
         "roofline": f64["roofline"],
+        "sweep_fp64_fraction": f64["sweep_fp64_fraction"],
         "hbm_gbs_algorithmic": f64["hbm_gbs_algorithmic"],
         "hbm_frac_algorithmic": f64["hbm_gbs_algorithmic"] / PEAK_HBM_GBS,
         "hbm_copy_gbs_measured": measured_copy_gbs(),

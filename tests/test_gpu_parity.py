@@ -326,6 +326,20 @@ def test_stage_parity_rough(H, orc, D, n):
     assert cnt["alg3"] > 0
 
 
+# two species in 3D: the other instantiations of the 3D sweeps (the y- and
+# z-sweeps' slim node record; x lines of 70 cells on 32 x 8 tiles of 31, 31
+# and 8 cells), transmissive and periodic, mixed and single-majority cells
+@pytest.mark.parametrize("n,bc,mixed", [((70, 6, 5), 0, False), ((70, 5, 6), 1, True)])
+def test_stage_parity_two_species_3d(H, orc, n, bc, mixed):
+    eos = I.eos_of(I.LIQ_A, I.AIR)
+    cells = int(np.prod(n))
+    W = I.random_admissible(eos, 3, cells, seed=500 + bc, p_range=(1e3, 1e10), u_scale=500.0, mixed=mixed)
+    W = W.reshape((W.shape[0], n[2], n[1], n[0]))
+    prob = I.Problem("rough_two_3d", eos, 3, tuple(n), (1e-3,) * 3, [(bc, bc)] * 3, np.ascontiguousarray(W))
+    cnt = check_stages(H, orc, prob, prob.W, counters="flips")
+    assert cnt["alg1"] + cnt["alg2"] + cnt["interp_hs"] + cnt["alg3"] > 0
+
+
 # degenerate and just-past-a-tile extents in 2D and 3D (x tiles hold 63 cells,
 # or 31 where that takes fewer face threads, as for 1..31 and 64 cells; y and
 # z tiles 15), transmissive and periodic

@@ -86,11 +86,13 @@ def test_fp32_config1_against_exact_riemann(H):
     assert errs[H.FP32] == pytest.approx(errs[H.FP64], rel=1e-3)
 
 
-def test_fp32_stage_against_oracle(H):
-    """One FP32 stage against the FP64 oracle: agreement at FP32 level."""
+@pytest.mark.parametrize("maker", ["config2_96x48", "config3_70"])
+def test_fp32_stage_against_oracle(H, maker):
+    """One FP32 stage against the FP64 oracle: agreement at FP32 level (in
+    3D at 70^3 the x lines take three 32 x 8 tiles, the last with 8 cells)."""
     import torch
     import oracle
-    prob = I.config2(96, 48)
+    prob = {"config2_96x48": lambda: I.config2(96, 48), "config3_70": lambda: I.config3(70)}[maker]()
     o = oracle.from_problem(prob)
     W0 = prob.W
     dt, lam = o.dt(W0, prob.cfl)

@@ -104,15 +104,26 @@ def counters_path(name):
 
 
 def kernel_source_hash() -> str:
-    """sha256 over the library's kernel sources (name, then contents, sorted)."""
-    import glob
+    """sha256 over the sources of the grid sweeps: csrc/hrm.hip and every
+    header it includes, directly or through another header (name, then
+    contents, sorted by name).  The ensemble and training kernels are other
+    translation units and do not enter it."""
     import hashlib
+    import re
+    dirs = [os.path.join(ROOT, "paper_2208_04488_amd", "csrc"), os.path.join(ROOT, "include")]
+    seen, todo = {}, ["hrm.hip"]
+    while todo:
+        name = todo.pop()
+        if name in seen:
+            continue
+        path = next(os.path.join(d, name) for d in dirs if os.path.exists(os.path.join(d, name)))
+        with open(path, "rb") as fh:
+            seen[name] = fh.read()
+        todo += re.findall(r'^#include "([^"]+)"', seen[name].decode(), re.M)
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2208_04488_amd", "csrc")
-    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp"))):
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+    for name in sorted(seen):
+        h.update(name.encode())
+        h.update(seen[name])
     return h.hexdigest()
 
 

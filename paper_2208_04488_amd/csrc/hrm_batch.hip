@@ -144,7 +144,9 @@ __global__ void __launch_bounds__(BS, 3) k_batch(const BatchArgs A)
                     __builtin_amdgcn_s_setprio(0);
                     __syncthreads();
                     double G[M], Gp[NA];
-                    {
+                    // a wave whose faces all lie beyond face n (the last tile of
+                    // a problem) skips them: no cell reads its slots
+                    if (c0 + (ts & ~63) <= n) {
                         unsigned lc = 0;  // packed counts of this face (cnt_one)
                         face_flux<N, D, 0, 1, FS, R, 0, false>(lds + ts, e, P, lam, G, Gp, lc);
                         const int f = c0 + ts;  // counted once, as in k_sweep

@@ -145,8 +145,10 @@ __global__ void __launch_bounds__(BS, 3) k_batch(const BatchArgs A)
                     __syncthreads();
                     double G[M], Gp[NA];
                     // a wave whose faces all lie beyond face n (the last tile of
-                    // a problem) skips them: no cell reads its slots
-                    if (c0 + (ts & ~63) <= n) {
+                    // a problem) skips them and leaves their slots, which no
+                    // cell reads, unwritten
+                    const bool live = c0 + (ts & ~63) <= n;
+                    if (live) {
                         unsigned lc = 0;  // packed counts of this face (cnt_one)
                         face_flux<N, D, 0, 1, FS, R, 0, false>(lds + ts, e, P, lam, G, Gp, lc);
                         const int f = c0 + ts;  // counted once, as in k_sweep
@@ -155,10 +157,12 @@ __global__ void __launch_bounds__(BS, 3) k_batch(const BatchArgs A)
                             for (int k = 0; k < C_N; ++k) cnt[k] += cnt_get(lc, k);
                     }
                     __syncthreads();
+                    if (live) {
 #pragma unroll
-                    for (int c = 0; c < M; ++c) lds[c * FS + ts] = G[c];
+                        for (int c = 0; c < M; ++c) lds[c * FS + ts] = G[c];
 #pragma unroll
-                    for (int k = 0; k < N - 1; ++k) lds[(M + k) * FS + ts] = Gp[k];
+                        for (int k = 0; k < N - 1; ++k) lds[(M + k) * FS + ts] = Gp[k];
+                    }
                     __syncthreads();
                     const int ci = c0 + ts;
                     if (ts < BS - 1 && ci < n) {
